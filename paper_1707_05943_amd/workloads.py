@@ -1,0 +1,135 @@
+"""Seeded synthetic workloads for the delay-PDE march.
+
+This module only names problem instances: grid sizes, physical parameters
+and seeded random draws.  It holds none of the scheme's arithmetic, so both
+the GPU path and the CPU oracle can take their inputs from it.
+
+Conventions (paper, Table 1 and App. B):
+  * Absolute units (hbar = c = 1).  Delta is the grid step in x and t.
+  * D = n_x = 2a/Delta is an even integer; a is re-derived as D*Delta/2.
+  * Columns j = 0..Nx sit at x_j = -a + j*Delta (j = 0 is x = -a); rows
+    r = 0..Nt sit at t_r = r*Delta.
+  * The incident two-photon state is a Gaussian packet phi with |phi|^2 of
+    standard deviation `width`, centred at x0 = -a - 8*width, carrier k0,
+    truncated to x <= -a, times a global phase exp(i*theta).  The emitter
+    frequency is on resonance with the carrier (omega0 = k0), and k0*a is
+    fixed per workload (App. B: omega0*a = k0*a = n*pi).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, asdict, field
+
+import numpy as np
+
+# incident families (Table 1 init_cond 1-3, plus the Gaussian packet)
+INC_PLANE = 1      # two-photon plane wave, Eqs. (5)-(6)
+INC_EXP1 = 2       # stimulated emission: one exponential photon, emitter excited, Eqs. (7)-(9)
+INC_EXP2 = 3       # two identical exponential photons, Eqs. (10)-(13)
+INC_GAUSS2 = 4     # two identical Gaussian photons
+
+
+@dataclass
+class Instance:
+    name: str
+    Nx: int
+    D: int
+    Nt: int
+    Delta: float
+    omega0: float
+    Gamma: float
+    incident: int = INC_GAUSS2
+    k: float = 0.0          # carrier wavenumber (absolute units)
+    alpha: float = 0.0      # exponential packet width, units of Gamma
+    x0: float = 0.0         # Gaussian centre
+    width: float = 1.0      # Gaussian std of |phi|^2
+    phase: float = 0.0      # global phase theta of the two-photon state
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def a(self) -> float:
+        return 0.5 * self.D * self.Delta
+
+    def as_dict(self) -> dict:
+        return asdict(self)
+
+
+def even_D(a: float, Delta: float) -> int:
+    """Number of grid steps in the round trip 2a, rounded to an even integer >= 2."""
+    return 2 * max(1, int(round(a / Delta)))
+
+
+def gaussian_instance(name: str, *, Gamma: float, two_a: float, Delta: float,
+                      k0a: float, width: float, Nx: int, Nt: int, seed: int) -> Instance:
+    D = even_D(0.5 * two_a, Delta)
+    a = 0.5 * D * Delta
+    k0 = k0a / a
+    rng = np.random.Generator(np.random.PCG64(seed))
+    theta = float(2.0 * math.pi * rng.random())
+    return Instance(name=name, Nx=int(Nx), D=D, Nt=int(Nt), Delta=float(Delta),
+                    omega0=k0, Gamma=float(Gamma), incident=INC_GAUSS2, k=k0,
+                    x0=-a - 8.0 * width, width=float(width), phase=theta, seed=seed)
+
+
+def small_gauss(seed: int = 1) -> Instance:
+    """D=100, Nx=4000, Nt=4000: Gamma=1, 2a=1, Delta=0.01, k0*a=pi/2, width 1."""
+    return gaussian_instance("gauss_D100_Nx4000_Nt4000", Gamma=1.0, two_a=1.0, Delta=0.01,
+                             k0a=0.5 * math.pi, width=1.0, Nx=4000, Nt=4000, seed=seed)
+
+
+def large_gauss(seed: int = 2) -> Instance:
+    """D=10000, Nx=262144, Nt=131072: Gamma=1, 2a=10, Delta=1e-3, k0*a=pi/2, width 1."""
+    return gaussian_instance("gauss_D10000_Nx262144_Nt131072", Gamma=1.0, two_a=10.0, Delta=1e-3,
+                             k0a=0.5 * math.pi, width=1.0, Nx=262144, Nt=131072, seed=seed)
+
+
+def with_sizes(inst: Instance, *, Nx: int | None = None, Nt: int | None = None,
+               name: str | None = None) -> Instance:
+    """Same physics and grid step, other box sizes (a column window or a row prefix)."""
+    d = inst.as_dict()
+    if Nx is not None:
+        d["Nx"] = int(Nx)
+    if Nt is not None:
+        d["Nt"] = int(Nt)
+    d["name"] = name or f"{inst.name}_Nx{d['Nx']}_Nt{d['Nt']}"
+    return Instance(**d)
+
+
+def tiny_gauss(D: int = 10, Nx: int = 64, Nt: int = 120, seed: int = 3,
+               Delta: float = 0.05, k0a: float = 0.5 * math.pi, width: float = 0.5,
+               Gamma: float = 1.0) -> Instance:
+    """Small grids for oracle cross-checks; x0 is moved close so the packet arrives early."""
+    a = 0.5 * D * Delta
+    k0 = k0a / a
+    rng = np.random.Generator(np.random.PCG64(seed))
+    theta = float(2.0 * math.pi * rng.random())
+    return Instance(name=f"tiny_D{D}_Nx{Nx}_Nt{Nt}", Nx=Nx, D=D, Nt=Nt, Delta=Delta,
+                    omega0=k0, Gamma=Gamma, incident=INC_GAUSS2, k=k0,
+                    x0=-a - 4.0 * width, width=width, phase=theta, seed=seed)
+
+
+def sweep_draw(n: int, seed: int) -> list[Instance]:
+    """Heterogeneous parameter sweep: Gamma*2a ~ U[0.1,10], k0*a ~ U[0,2pi),
+    width ~ logU[0.2,5]/Gamma, Delta in {0.01, 0.005, 0.002}; Nx is the power of
+    two that holds the strip, the packet and its decay (clamped to 1024..16384),
+    Nt = 4*Nx."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    Gamma = 1.0
+    for i in range(n):
+        two_a = float(rng.uniform(0.1, 10.0)) / Gamma
+        k0a = float(rng.uniform(0.0, 2.0 * math.pi))
+        width = float(math.exp(rng.uniform(math.log(0.2), math.log(5.0)))) / Gamma
+        Delta = float(rng.choice([0.01, 0.005, 0.002]))
+        theta = float(2.0 * math.pi * rng.random())
+        D = even_D(0.5 * two_a, Delta)
+        a = 0.5 * D * Delta
+        need = max(2 * D, int(math.ceil((16 * width + 2 * a + 10.0 / Gamma) / (4 * Delta))))
+        Nx = 1 << max(0, (need - 1).bit_length())
+        Nx = min(max(Nx, 1024), 16384)
+        k0 = k0a / a
+        out.append(Instance(name=f"sweep{seed}_{i}", Nx=Nx, D=D, Nt=4 * Nx, Delta=Delta,
+                            omega0=k0, Gamma=Gamma, incident=INC_GAUSS2, k=k0,
+                            x0=-a - 8.0 * width, width=width, phase=theta, seed=seed * 100003 + i))
+    return out
