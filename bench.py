@@ -1,0 +1,137 @@
+"""Benchmark: FP64 FDTD march of the 1+1D delay PDE on one MI355X.
+
+One step = the whole hot path over one instance: the boundary tables
+(gamma-function delay series for E(t_r)), the march over every row, and the
+readouts (P_e(t_r) for all rows, chi at the detectors).  Inputs are synthetic
+and already resident (the workspace lives in HBM before timing starts).
+
+Prints one JSON line.  `value` is cell updates per second of the whole step;
+`roofline` is the dominant kernel (the march) against the HBM peak, its
+duration measured with events on the stream it runs on; `cpu_baseline` is the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FDTD cell-updates/s + % HBM roofline; sweep points/s at 1e-3 err (surrogate vs plain)"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=600, help="rows past D in the oracle's sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(inst, extra_rows: int) -> dict:
+    """The oracle as it stands, single-threaded, on a column window of the
+    same instance (columns 0..2D+1100, rows 1..D+extra_rows)."""
+    import oracle
+    from paper_1707_05943_amd import workloads as W
+    win = W.with_sizes(inst, Nx=min(inst.Nx, 2 * inst.D + 1100), Nt=min(inst.Nt, inst.D + extra_rows))
+    t0 = time.perf_counter()
+    E = oracle.E_table(win)
+    t1 = time.perf_counter()
+    oracle.march(win, E, want_ring=False)
+    t2 = time.perf_counter()
+    cells = win.Nx * win.Nt
+    return {"value": cells / (t2 - t1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"march of columns 1..{win.Nx} over rows 1..{win.Nt} of {inst.name} "
+                      f"({cells:.3g} cells, {t2 - t1:.1f} s; boundary table {t1 - t0:.1f} s not counted)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1707_05943_amd import fdtd
+    from paper_1707_05943_amd import workloads as W
+
+    inst = W.large_gauss() if args.workload == "large" else W.small_gauss()
+    dev = torch.device("cuda:0")
+    sol = fdtd.Solver(inst, device=str(dev))
+    stream = torch.cuda.current_stream(dev)
+    n_tau = 1024
+    pe_dev = torch.empty(inst.Nt + 1, dtype=torch.float64, device=dev)
+    chi_dev = torch.empty(2 * n_tau, dtype=torch.float64, device=dev)
+    lib = sol.lib
+
+    def step(ev=None):
+        sol._check(lib.fdtd_set_boundary(sol.ctx))
+        if ev is not None:
+            ev[0].record(stream)
+        sol._check(lib.fdtd_march(sol.ctx, inst.Nt))
+        if ev is not None:
+            ev[1].record(stream)
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_PE, 0, ctypes.c_void_p(pe_dev.data_ptr()),
+                                    inst.Nt + 1, 1))
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_CHI, 0, ctypes.c_void_p(chi_dev.data_ptr()),
+                                    n_tau, 1))
+
+    print(f"[bench] {inst.name}: warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    march_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    cells = inst.Nx * inst.Nt
+    value = cells / (ms_step * 1e-3)
+    # the march kernel: one launch per row; algorithmic bytes per row
+    # 32 (Nx + D): 16 B written and 16 B of the delay row read per column,
+    # 32 B per strip column for the mirrored source reads
+    launches = inst.Nt
+    bytes_per_launch = 32.0 * (inst.Nx + inst.D)
+    avg_launch_s = march_ms * 1e-3 / launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    pe = pe_dev.cpu().numpy()
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": inst.name, "D": inst.D, "Nx": inst.Nx, "Nt": inst.Nt, "Delta": inst.Delta,
+                   "incident": "gaussian two-photon", "ring_GB": (inst.D + 2) * (inst.Nx + 1) * 16 / 1e9,
+                   "march_ms": march_ms, "pe_max": float(np.max(pe))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_row", "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6},
+    }
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) FDTD solver for the 1+1D delay PDE
+ * of waveguide QED (Fang, "FDTD: solving 1+1D delay PDE in parallel",
+ * arXiv:1707.05943).
+ *
+ * The library marches Eq. (1) of the paper on a square grid dx = dt = Delta
+ * (Sec. 2), with the line-1 terms (time and space derivatives, W psi and the
+ * delay term) discretised by "squares" (Eq. 3) and the source terms of lines
+ * 2-3 by "bars" (Eq. 4).  The region x <= -a is not marched: its values are
+ * the exact solution psi(x,t) = c phi(x-t) E(t) (Eqs. 5, 8, 12), with E(t)
+ * the one-excitation amplitude (Eqs. 6, 9, 13), which involves the lower
+ * incomplete Gamma function gamma(n, z) of App. C.
+ *
+ * Grid.  Columns j = 0..Nx sit at x_j = -a + j*Delta (j = 0 is x = -a);
+ * rows r = 0..Nt at t_r = r*Delta.  D = 2a/Delta (the paper's n_x, Table 1)
+ * is an even integer; columns 1..D are the mirror strip -a < x <= a, columns
+ * beyond D the outgoing region.  Row 0 is the initial condition psi(x,0) = 0
+ * for x > -a.  All values are complex double, stored as (re, im) pairs.
+ *
+ * Memory.  The caller allocates and owns every device buffer: it passes one
+ * device workspace of at least fdtd_workspace_size() bytes, which must stay
+ * alive and untouched until fdtd_destroy().  The context holds views only.
+ * Inside, the march keeps a ring of D+2 rows (the delay term reaches back
+ * D+1 rows; every older value it needs lies in x <= -a and comes from the
+ * exact solution), so memory does not grow with Nt.
+ *
+ * Streams.  Every call enqueues its work on the HIP stream given to
+ * fdtd_init and returns without waiting, except where stated.  A context is
+ * not thread-safe; distinct contexts are independent.
+ *
+ * Errors.  Every call returns FDTD_OK (0) or a negative code; the text of the
+ * last failure of a context is available from fdtd_last_error().
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDTD_ABI_VERSION 1u
+
+enum fdtd_status {
+    FDTD_OK = 0,
+    FDTD_EINVAL = -1,   /* invalid parameters (D odd or < 2, Nx < D+1, Delta <= 0, Gamma <= 0, non-finite) */
+    FDTD_ESIZE = -2,    /* workspace too small, or an output buffer too short */
+    FDTD_ESTATE = -3,   /* call out of order (march before boundary), or a row no longer held */
+    FDTD_EDEVICE = -4,  /* a HIP runtime error */
+    FDTD_ERANGE = -5    /* gamma(n,z) series out of range, or a non-finite boundary value */
+};
+
+/* Incident states (Table 1 "init_cond" 1-3, plus a Gaussian two-photon packet). */
+enum fdtd_incident {
+    FDTD_INC_PLANE = 1,  /* two-photon plane wave e^{ik(x1+x2)}, Eqs. (5)-(6), A = 1 */
+    FDTD_INC_EXP1 = 2,   /* stimulated emission: one exponential photon, emitter excited, Eqs. (7)-(9) */
+    FDTD_INC_EXP2 = 3,   /* two identical exponential photons, Eqs. (10)-(13) */
+    FDTD_INC_GAUSS2 = 4  /* two identical Gaussian photons, phi ~ exp(-(x-x0)^2/(4 w^2) + i k (x-x0)) for x <= -a */
+};
+
+typedef struct fdtd_params {
+    uint32_t abi_version;   /* FDTD_ABI_VERSION */
+    uint32_t struct_size;   /* sizeof(fdtd_params) */
+    int64_t Nx;             /* last column; columns 0..Nx; Nx >= D+1 */
+    int64_t D;              /* 2a/Delta, even, >= 2 (Table 1 n_x) */
+    int64_t Nt;             /* last row; rows 0..Nt (Table 1 N_y = Nt+1) */
+    double Delta;           /* grid step in x and t (absolute units, hbar = c = 1) */
+    double omega0;          /* emitter frequency */
+    double Gamma;           /* emitter decay rate */
+    int32_t incident;       /* enum fdtd_incident */
+    int32_t reserved0;      /* must be 0 */
+    double k;               /* carrier wavenumber of the incident packet */
+    double alpha;           /* exponential packet width, units of Gamma (Eq. 7) */
+    double x0;              /* Gaussian centre (x0 <= -a) */
+    double width;           /* Gaussian: standard deviation of |phi|^2 */
+    double phase;           /* global phase theta of the incident two-photon state */
+} fdtd_params;
+
+typedef struct fdtd_ctx fdtd_ctx;
+
+/* Bytes of device workspace needed for these parameters (ring, boundary
+ * tables, per-row reductions).  Returns FDTD_EINVAL on bad parameters. */
+int fdtd_workspace_size(const fdtd_params *p, size_t *bytes);
+
+/* Validate parameters, carve the caller's workspace (device pointer, at
+ * least fdtd_workspace_size bytes, 256-byte aligned) and bind the HIP stream
+ * (a hipStream_t; NULL is the default stream).  On success *out receives a
+ * new context; free it with fdtd_destroy.  Enqueues the clearing of the ring. */
+int fdtd_init(const fdtd_params *p, void *d_workspace, size_t bytes, void *hip_stream, fdtd_ctx **out);
+
+/* Compute the boundary tables on the device (Sec. 2, Eqs. 5-13, App. C):
+ * E(t_r) for r = 0..Nt from the delay series of the one-excitation problem
+ * -- the closed forms with gamma(n+1, z) for the plane-wave and exponential
+ * families, and for the Gaussian a superposition of plane-wave solutions
+ * over the packet's Fourier components -- plus phi on the grid, the drive
+ * and the exact part of int |psi|^2.  Resets the march to row 0. */
+int fdtd_set_boundary(fdtd_ctx *ctx);
+
+/* Test hook: as fdtd_set_boundary, but E(t_r) (r = 0..n-1, n = Nt+1) is
+ * copied from the caller's host array of complex doubles (n pairs). */
+int fdtd_set_boundary_tables(fdtd_ctx *ctx, const double *h_E, int64_t n);
+
+/* Advance the march by n_rows rows (resumable: the row counter lives in the
+ * context).  Rows past Nt are not marched (FDTD_ESTATE).  Returns after
+ * enqueueing the work. */
+int fdtd_march(fdtd_ctx *ctx, int64_t n_rows);
+
+/* Current row (the last row solved; 0 right after set_boundary). */
+int fdtd_current_row(const fdtd_ctx *ctx, int64_t *row);
+
+enum fdtd_readout_kind {
+    FDTD_RO_ROW = 1,   /* arg = row rho (current-D-1 <= rho <= current); count = Nx+1 values psi(j, rho),
+                          column 0 from the exact solution */
+    FDTD_RO_PE = 2,    /* P_e(t_r) = int |psi(x,t_r)|^2 dx for r = 0..count-1 (count <= current+1), doubles:
+                          the exact part x <= -a plus the trapezoid rule over columns 0..Nx */
+    FDTD_RO_CHI = 3,   /* chi(x1, x2, t) of Eq. (2) at the current row, detectors x1 = a + Delta,
+                          x2 = x1 + k Delta for k = 0..count-1 (count <= Nx-D) */
+    FDTD_RO_E = 4      /* the boundary table c E(t_r), r = 0..count-1 (count <= Nt+1); c = sqrt(2) e^{i theta}
+                          for two photons, 1 for stimulated emission */
+};
+
+/* Copy a readout into dst: a device pointer (dst_on_device = 1, enqueued on
+ * the context's stream) or a host pointer (dst_on_device = 0; the call then
+ * waits for the stream).  Complex outputs are (re, im) pairs. */
+int fdtd_readout(fdtd_ctx *ctx, int32_t what, int64_t arg, void *dst, int64_t count, int32_t dst_on_device);
+
+/* Wait for all work of this context. */
+int fdtd_sync(fdtd_ctx *ctx);
+
+/* Free the context (not the workspace).  Accepts NULL. */
+int fdtd_destroy(fdtd_ctx *ctx);
+
+/* Static text for a status code; text of the last failure of ctx (or of the
+ * last failed fdtd_init / fdtd_workspace_size when ctx is NULL). */
+const char *fdtd_strerror(int status);
+const char *fdtd_last_error(const fdtd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDTD_H */

@@ -417,20 +417,19 @@ void orc_E_table(const orc_params *p, int mode, cplx *E)
 typedef struct {
     const orc_params *p;
     const cplx *E;           /* E(t_r), r = 0..Nt */
+    const cplx *phig;        /* phi(-a - q Delta), q = 0..Nt: phi at the grid points x - t of x <= -a */
+    cplx c_ex;               /* psi = c_ex phi(x-t) E(t) in x <= -a */
     cplx *ring;              /* (D+2) rows of Nx+1 columns; row rho in slot rho mod (D+2) */
     int64_t cur;             /* row being solved */
     int fault;               /* set when a read violates the ring's lag bound */
 } orc_state;
 
 /* exact solution in x <= -a (Eq. 12 for identical photons, Eq. 8 for
- * stimulated emission): psi(x,t) = c phi(x-t) E(t) */
+ * stimulated emission): psi(x,t) = c phi(x-t) E(t); on the grid
+ * x_i - t_rho = -a - (rho - i) Delta */
 static cplx psi_exact(const orc_state *s, int64_t i, int64_t rho)
 {
-    const orc_params *p = s->p;
-    double x = -half_a(p) + (double)i * p->Delta;
-    double t = (double)rho * p->Delta;
-    cplx c = (p->incident == INC_EXP1) ? 1.0 : sqrt(2.0) * cexp(I * p->phase);
-    return c * orc_phi(p, x - t) * s->E[rho];
+    return s->c_ex * s->phig[rho - i] * s->E[rho];
 }
 
 /* psi at grid column i (x_i = -a + i Delta) and row rho: zero before t = 0;
@@ -444,13 +443,6 @@ static cplx psi_at(orc_state *s, int64_t i, int64_t rho)
     int64_t lag = s->cur - rho;
     if (lag < 0 || lag > p->D + 1) { s->fault = 1; return NAN; }
     return s->ring[(rho % (p->D + 2)) * (p->Nx + 1) + i];
-}
-
-/* the incident two-photon amplitude chi(x1, x2, 0) */
-static cplx chi0(const orc_params *p, double x1, double x2)
-{
-    if (p->incident == INC_EXP1) return 0.0;
-    return cexp(I * p->phase) * orc_phi(p, x1) * orc_phi(p, x2);
 }
 
 /* the bar of Eq. (4): f at the midpoint of columns i and i+1 */
@@ -469,7 +461,8 @@ static cplx bar(orc_state *s, int64_t i, int64_t rho)
  *   source terms (lines 2-3) -> bars: their time argument falls on a grid row
  *       and their space argument midway between two columns
  *   drive (line 4) -> chi(x-t, -/+a - t, 0) evaluated at the centre.  */
-static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1, r) */)
+static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1, r) */,
+                       cplx drive_row /* phi(-a - t_c) - phi(a - t_c) */)
 {
     const orc_params *p = s->p;
     const int64_t D = p->D;
@@ -497,11 +490,12 @@ static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1,
      * 2D-j+1; theta(x_c - a) holds iff j >= D+1. */
     if (j >= D + 1 && r - j + D >= 0) src += bar(s, 2 * D - j, r - j + D) - bar(s, D - j, r - j + D);
     rhs -= (G / 2.0) * src;
-    /* drive: sqrt(G) [chi0(x-t, -a-t) - chi0(x-t, a-t)] at the centre */
-    {
-        double xc = -a + ((double)j - 0.5) * dl, tc = ((double)r - 0.5) * dl;
-        rhs += sqrt(G) * (chi0(p, xc - tc, -a - tc) - chi0(p, xc - tc, a - tc));
-    }
+    /* drive: sqrt(G) [chi0(x-t, -a-t) - chi0(x-t, a-t)] at the centre, where
+     * x_c - t_c = x_j - t_r lies on the grid (phi there is phig[r - j]) and
+     * phi(-a - t_c), phi(a - t_c) are the same for the whole row */
+    if (p->incident != INC_EXP1 && r - j >= 0)
+        rhs += sqrt(G) * cexp(I * p->phase) * s->phig[r - j] * drive_row;
+    (void)a; (void)dl;
     /* (U - bl)/Delta + (W/4)(bl + br + tl + U) = rhs */
     return (rhs + bl / dl - (W / 4.0) * (bl + br + tl)) / (1.0 / dl + W / 4.0);
 }
@@ -515,8 +509,11 @@ static cplx chi_detector(orc_state *s, int64_t r, int64_t kk)
     const int64_t D = p->D;
     const double dl = p->Delta, a = half_a(p), G = p->Gamma;
     const int64_t j1 = D + 1, j2 = D + 1 + kk;
-    double x1 = -a + j1 * dl, x2 = -a + j2 * dl, t = r * dl;
-    cplx c0 = chi0(p, x1 - t, x2 - t);
+    /* chi(x1 - t, x2 - t, 0) = e^{i theta} phi(x1 - t) phi(x2 - t); x_j - t_r = -a - (r - j) Delta */
+    cplx c0 = 0.0;
+    if (p->incident != INC_EXP1 && r - j1 >= 0 && r - j2 >= 0)
+        c0 = cexp(I * p->phase) * s->phig[r - j1] * s->phig[r - j2];
+    (void)a; (void)dl;
     cplx acc = 0.0;
     /* psi(x1 - x2 - a, t - x2 - a): column j1 - j2, row r - j2 */
     acc += psi_at(s, j1 - j2, r - j2);
@@ -576,9 +573,13 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
               const int64_t *snap_rows, int64_t n_snap, cplx *snaps)
 {
     const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt, R = D + 2, C = Nx + 1;
-    orc_state s = { p, E, NULL, 0, 0 };
+    orc_state s = { p, E, NULL, 0.0, NULL, 0, 0 };
     s.ring = (cplx *)calloc((size_t)(R * C), sizeof(cplx));
-    if (!s.ring) return -2;
+    cplx *phig = (cplx *)malloc(sizeof(cplx) * (size_t)(Nt + 1));
+    if (!s.ring || !phig) { free(s.ring); free(phig); return -2; }
+    for (int64_t q = 0; q <= Nt; ++q) phig[q] = orc_phi(p, -half_a(p) - (double)q * p->Delta);
+    s.phig = phig;
+    s.c_ex = (p->incident == INC_EXP1) ? 1.0 : sqrt(2.0) * cexp(I * p->phase);
 
     /* row 0: psi(x, 0) = 0 for x > -a in every family */
     s.cur = 0;
@@ -595,8 +596,10 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
         cplx *row = s.ring + (r % R) * C;
         row[0] = 0.0;              /* column 0 is read from the exact solution */
         cplx left = psi_at(&s, 0, r);
+        double tc = ((double)r - 0.5) * p->Delta;
+        cplx drive_row = orc_phi(p, -half_a(p) - tc) - orc_phi(p, half_a(p) - tc);
         for (int64_t j = 1; j <= Nx; ++j) {
-            cplx u = solve_cell(&s, j, r, left);
+            cplx u = solve_cell(&s, j, r, left, drive_row);
             row[j] = u;
             left = u;
         }
@@ -618,6 +621,7 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
         }
     }
     free(s.ring);
+    free(phig);
     return s.fault ? -1 : 0;
 }
 

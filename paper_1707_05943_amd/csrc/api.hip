@@ -1,0 +1,318 @@
+// Host side of the C ABI declared in include/fdtd.h.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "fdtd_common.h"
+
+static char g_err[512];
+
+static int fail(fdtd_ctx* c, int code, const char* fmt, ...)
+{
+    char* dst = c ? c->err : g_err;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int64_t align256(int64_t n) { return (n + 255) & ~(int64_t)255; }
+
+// Scheme coefficients of the solved square (Eq. 3): with
+// d = 1/Delta + W/4, psi(j,r) = alpha psi(j-1,r) + cA psi(j-1,r-1) + cB psi(j,r-1) + S/d.
+static void coefficients(const fdtd_params* p, Geom* g)
+{
+    const cd W = mk(0.5 * p->Gamma, p->omega0);
+    const cd d = mk(1.0 / p->Delta, 0.0) + 0.25 * W;
+    g->W = W;
+    g->cinv = cdiv(mk(1.0, 0.0), d);
+    g->alpha = (-0.25 * W) * g->cinv;
+    g->cB = g->alpha;
+    g->cA = (mk(1.0 / p->Delta, 0.0) - 0.25 * W) * g->cinv;
+}
+
+// columns recomputed left of a block so that the dropped term alpha^halo U is
+// below 2^-60 relative
+static int halo_for(cd alpha)
+{
+    const double m = cabs_(alpha);
+    if (m == 0.0) return 1;
+    const double h = ceil(log(ldexp(1.0, -60)) / log(m));
+    return h < 1.0 ? 1 : (int)h;
+}
+
+static int validate(const fdtd_params* p, char* why, size_t n)
+{
+    if (!p) { snprintf(why, n, "params is NULL"); return FDTD_EINVAL; }
+    if (p->abi_version != FDTD_ABI_VERSION || p->struct_size != sizeof(fdtd_params)) {
+        snprintf(why, n, "abi_version/struct_size mismatch (%u/%u, expected %u/%zu)", p->abi_version,
+                 p->struct_size, FDTD_ABI_VERSION, sizeof(fdtd_params));
+        return FDTD_EINVAL;
+    }
+    if (p->D < 2 || (p->D & 1)) { snprintf(why, n, "D = %lld must be even and >= 2", (long long)p->D); return FDTD_EINVAL; }
+    if (p->Nx < p->D + 1) { snprintf(why, n, "Nx = %lld must be >= D+1", (long long)p->Nx); return FDTD_EINVAL; }
+    if (p->Nt < 1) { snprintf(why, n, "Nt must be >= 1"); return FDTD_EINVAL; }
+    if (!(p->Delta > 0.0) || !(p->Gamma > 0.0) || !isfinite(p->Delta) || !isfinite(p->Gamma) ||
+        !isfinite(p->omega0) || !isfinite(p->k) || !isfinite(p->alpha) || !isfinite(p->x0) ||
+        !isfinite(p->width) || !isfinite(p->phase)) {
+        snprintf(why, n, "Delta and Gamma must be > 0 and every parameter finite");
+        return FDTD_EINVAL;
+    }
+    if (p->incident < FDTD_INC_PLANE || p->incident > FDTD_INC_GAUSS2) {
+        snprintf(why, n, "unknown incident family %d", p->incident);
+        return FDTD_EINVAL;
+    }
+    if ((p->incident == FDTD_INC_EXP1 || p->incident == FDTD_INC_EXP2) && !(p->alpha > 0.0)) {
+        snprintf(why, n, "exponential packets need alpha > 0");
+        return FDTD_EINVAL;
+    }
+    if (p->incident == FDTD_INC_GAUSS2 && (!(p->width > 0.0) || p->x0 > -0.5 * p->D * p->Delta)) {
+        snprintf(why, n, "Gaussian packets need width > 0 and x0 <= -a");
+        return FDTD_EINVAL;
+    }
+    Geom g;
+    coefficients(p, &g);
+    if (halo_for(g.alpha) > MAX_HALO) {
+        snprintf(why, n, "|alpha| = %.3g needs a halo of more than %d columns: Delta too coarse for |W|",
+                 cabs_(g.alpha), MAX_HALO);
+        return FDTD_EINVAL;
+    }
+    return FDTD_OK;
+}
+
+struct Layout {
+    int64_t ring, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, total;
+};
+
+static Layout layout(const fdtd_params* p, int64_t nblk)
+{
+    Layout L;
+    const int64_t C = p->Nx + 1, R = p->D + 2, n = p->Nt + 1;
+    int64_t off = 0;
+    L.ring = off; off += align256(R * C * 16);
+    L.Et = off; off += align256(n * 16);
+    L.Phi = off; off += align256(n * 16);
+    L.Drv = off; off += align256(n * 16);
+    L.Pex = off; off += align256(n * 8);
+    L.Ppart = off; off += align256(n * nblk * 8);
+    L.Pe = off; off += align256(n * 8);
+    L.chi = off; off += align256(C * 16);
+    L.Ebuf = off; off += align256(n * 16);
+    L.status = off; off += 256;
+    L.total = off;
+    return L;
+}
+
+static int64_t blocks_per_row(const fdtd_params* p) { return (p->Nx + MARCH_TX - 1) / MARCH_TX; }
+
+extern "C" {
+
+int fdtd_workspace_size(const fdtd_params* p, size_t* bytes)
+{
+    char why[256];
+    int rc = validate(p, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    if (!bytes) return fail(nullptr, FDTD_EINVAL, "bytes is NULL");
+    *bytes = (size_t)layout(p, blocks_per_row(p)).total;
+    return FDTD_OK;
+}
+
+int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_stream, fdtd_ctx** out)
+{
+    char why[256];
+    int rc = validate(p, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    if (!out) return fail(nullptr, FDTD_EINVAL, "out is NULL");
+    *out = nullptr;
+    const int64_t nblk = blocks_per_row(p);
+    Layout L = layout(p, nblk);
+    if (!d_workspace || bytes < (size_t)L.total)
+        return fail(nullptr, FDTD_ESIZE, "workspace of %zu bytes is smaller than the %lld needed", bytes,
+                    (long long)L.total);
+    if (((uintptr_t)d_workspace) & 255) return fail(nullptr, FDTD_EINVAL, "workspace must be 256-byte aligned");
+
+    fdtd_ctx* c = (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx));
+    if (!c) return fail(nullptr, FDTD_EDEVICE, "out of host memory");
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->nblk = nblk;
+    Geom& g = c->g;
+    g.Nx = p->Nx; g.D = p->D; g.Nt = p->Nt; g.C = p->Nx + 1; g.R = p->D + 2;
+    g.Delta = p->Delta; g.a = 0.5 * (double)p->D * p->Delta; g.Gamma = p->Gamma;
+    coefficients(p, &g);
+    g.halo = halo_for(g.alpha);
+
+    Packet& pk = c->pk;
+    pk.incident = p->incident; pk.k = p->k; pk.alpha = p->alpha; pk.x0 = p->x0; pk.width = p->width;
+    pk.phase = p->phase; pk.Gamma = p->Gamma; pk.a = g.a;
+    const cd eth = mk(cos(p->phase), sin(p->phase));
+    if (p->incident == FDTD_INC_EXP1) {
+        pk.c_ex = mk(1.0, 0.0);      // Eq. (8): psi = phi(x-t) e1(t)
+        pk.c_drive = mk(0.0, 0.0);   // no two-photon component
+    } else {
+        pk.c_ex = sqrt(2.0) * eth;   // Eq. (12), identical photons: sqrt(2) phi(x-t) E(t)
+        pk.c_drive = sqrt(p->Gamma) * eth;
+    }
+
+    char* base = (char*)d_workspace;
+    Bufs& b = c->b;
+    b.ring = (cd*)(base + L.ring);
+    b.Et = (cd*)(base + L.Et);
+    b.Phi = (cd*)(base + L.Phi);
+    b.Drv = (cd*)(base + L.Drv);
+    b.Pex = (double*)(base + L.Pex);
+    b.Ppart = (double*)(base + L.Ppart);
+    b.Pe = (double*)(base + L.Pe);
+    b.chi = (cd*)(base + L.chi);
+    b.Ebuf = (cd*)(base + L.Ebuf);
+    b.status = (int*)(base + L.status);
+    c->row = -1;
+    c->boundary_ready = 0;
+    rc = launch_clear(c);
+    if (rc) { free(c); return fail(nullptr, rc, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError())); }
+    *out = c;
+    return FDTD_OK;
+}
+
+static int check_status(fdtd_ctx* c)
+{
+    int st = 0;
+    hipError_t e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+    if (st & STATUS_GAMMA_RANGE) return fail(c, FDTD_ERANGE, "gamma(n,z) series out of range");
+    if (st & STATUS_NONFINITE) return fail(c, FDTD_ERANGE, "non-finite boundary value");
+    return FDTD_OK;
+}
+
+int fdtd_set_boundary(fdtd_ctx* c)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    int rc = launch_boundary(c, 0);
+    if (rc) return fail(c, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = check_status(c);
+    if (rc) return rc;
+    c->row = 0;
+    c->boundary_ready = 1;
+    return FDTD_OK;
+}
+
+int fdtd_set_boundary_tables(fdtd_ctx* c, const double* h_E, int64_t n)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    if (!h_E || n != c->p.Nt + 1) return fail(c, FDTD_ESIZE, "expected Nt+1 = %lld values", (long long)(c->p.Nt + 1));
+    hipError_t e = hipMemcpyAsync(c->b.Ebuf, h_E, (size_t)n * 16, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "copy of E failed: %s", hipGetErrorString(e));
+    int rc = launch_boundary(c, 1);
+    if (rc) return fail(c, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = check_status(c);
+    if (rc) return rc;
+    c->row = 0;
+    c->boundary_ready = 1;
+    return FDTD_OK;
+}
+
+int fdtd_march(fdtd_ctx* c, int64_t n_rows)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    if (!c->boundary_ready) return fail(c, FDTD_ESTATE, "march before set_boundary");
+    if (n_rows < 0) return fail(c, FDTD_EINVAL, "n_rows < 0");
+    if (c->row + n_rows > c->p.Nt) return fail(c, FDTD_ESTATE, "march past Nt = %lld", (long long)c->p.Nt);
+    if (n_rows == 0) return FDTD_OK;
+    int rc = launch_march_rows(c, c->row + 1, c->row + n_rows);
+    if (rc) return fail(c, rc, "march launch failed: %s", hipGetErrorString(hipGetLastError()));
+    c->row += n_rows;
+    return FDTD_OK;
+}
+
+int fdtd_current_row(const fdtd_ctx* c, int64_t* row)
+{
+    if (!c || !row) return FDTD_EINVAL;
+    *row = c->row;
+    return FDTD_OK;
+}
+
+int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t count, int32_t dst_on_device)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    if (!dst || count < 0) return fail(c, FDTD_EINVAL, "bad destination");
+    if (!c->boundary_ready) return fail(c, FDTD_ESTATE, "readout before set_boundary");
+    size_t esz = 16;
+    void* src = nullptr;
+    int rc = FDTD_OK;
+    switch (what) {
+    case FDTD_RO_ROW:
+        if (count != c->p.Nx + 1) return fail(c, FDTD_ESIZE, "a row has Nx+1 = %lld values", (long long)(c->p.Nx + 1));
+        if (arg < 0 || arg > c->row || arg < c->row - (c->p.D + 1))
+            return fail(c, FDTD_ESTATE, "row %lld is not held (current %lld)", (long long)arg, (long long)c->row);
+        if (dst_on_device) return launch_row_readout(c, arg, (cd*)dst) ? fail(c, FDTD_EDEVICE, "launch failed") : FDTD_OK;
+        // stage through the chi scratch (it holds Nx+1 values)
+        rc = launch_row_readout(c, arg, c->b.chi);
+        src = c->b.chi;
+        break;
+    case FDTD_RO_PE:
+        esz = 8;
+        if (count > c->row + 1) return fail(c, FDTD_ESTATE, "only %lld rows marched", (long long)(c->row + 1));
+        rc = launch_pe_final(c, count, dst_on_device ? (double*)dst : c->b.Pe);
+        if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
+        src = c->b.Pe;
+        break;
+    case FDTD_RO_CHI:
+        if (count > c->p.Nx - c->p.D) return fail(c, FDTD_ESIZE, "at most Nx-D = %lld detector separations",
+                                                  (long long)(c->p.Nx - c->p.D));
+        rc = launch_chi(c, c->row, count, dst_on_device ? (cd*)dst : c->b.chi);
+        if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
+        src = c->b.chi;
+        break;
+    case FDTD_RO_E:
+        if (count > c->p.Nt + 1) return fail(c, FDTD_ESIZE, "E has Nt+1 values");
+        if (dst_on_device) {
+            hipError_t e = hipMemcpyAsync(dst, c->b.Et, (size_t)count * 16, hipMemcpyDeviceToDevice, c->stream);
+            return e == hipSuccess ? FDTD_OK : fail(c, FDTD_EDEVICE, "%s", hipGetErrorString(e));
+        }
+        src = c->b.Et;
+        break;
+    default:
+        return fail(c, FDTD_EINVAL, "unknown readout %d", what);
+    }
+    if (rc) return fail(c, rc, "readout launch failed");
+    hipError_t e = hipMemcpyAsync(dst, src, (size_t)count * esz, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "readout copy failed: %s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+int fdtd_sync(fdtd_ctx* c)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "%s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+int fdtd_destroy(fdtd_ctx* c)
+{
+    free(c);
+    return FDTD_OK;
+}
+
+const char* fdtd_strerror(int s)
+{
+    switch (s) {
+    case FDTD_OK: return "ok";
+    case FDTD_EINVAL: return "invalid argument";
+    case FDTD_ESIZE: return "buffer too small";
+    case FDTD_ESTATE: return "call out of order";
+    case FDTD_EDEVICE: return "HIP device error";
+    case FDTD_ERANGE: return "value out of range";
+    }
+    return "unknown status";
+}
+
+const char* fdtd_last_error(const fdtd_ctx* c) { return c ? c->err : g_err; }
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+// Boundary tables of the march: the exact solution in x <= -a.
+//
+// In x <= -a the two-excitation amplitude is psi(x,t) = c phi(x-t) E(t)
+// (Eqs. 5, 8, 12 for identical photons), where E(t) is the one-excitation
+// emitter amplitude driven by the packet phi.  E solves a linear delay
+// equation whose solution is a series over round trips 2a (Eqs. 6, 9, 13):
+//
+//   E(t) = sqrt(G/2) sum_{m>=0} (G/2)^m [J_m(t - 2ma) - J_m(t - 2(m+1)a)],
+//   J_m(T) = int_0^T (T-s)^m/m! e^{-W(T-s)} phi(-a-s) ds.
+//
+// For phi(-a-s) = A e^{-ika} e^{-lambda s} (plane wave: lambda = ik; the
+// exponential packet of Eq. 7: lambda = ik + alpha G/2) this integral is an
+// incomplete Gamma function, J_m(T) = A e^{-ika} e^{-lambda T} T^{m+1}
+// gamma*(m+1, bT) with b = W - lambda and gamma*(n,z) = z^{-n} gamma(n,z)/(n-1)!.
+// Grouping the two J's that share T_m = t - 2ma and using
+// gamma*(m,z) = z gamma*(m+1,z) + e^{-z}/m! gives one gamma* per term:
+//
+//   term_0 = e^{-lambda T} T gamma*(1, bT)
+//   term_m = e^{-lambda T} (G/2)^{m-1} T^m [(G/2 - b) T gamma*(m+1, bT)] - (G/2)^{m-1} T^m e^{-W T}/m!
+//
+// which is Eq. (6) (and Eq. 13 times e^{-ika}) rearranged.  The Gaussian
+// packet has no closed form; it is a superposition of plane waves,
+// phi(x) = int dk c(k) e^{ikx}, and since the truncation x <= -a is common to
+// every plane wave, E is the same superposition of plane-wave solutions.  The
+// k-integral is a trapezoid sum whose spacing h puts the periodic images of
+// the packet (at x0 +- 2 pi/h) outside the part of x <= -a that reaches the
+// emitter before the last row.
+//
+// gamma*(n, z) for integer n >= 1 (App. C): for |z| <= n the series
+// e^{-z} sum_k z^k/Gamma(n+k+1), whose terms decrease from the first; beyond,
+// the terminating form z^{-n} - e^{-z} sum_{k<n} z^{k-n}/k! (exact for integer
+// n), whose terms grow towards the last one.
+
+#include "fdtd_common.h"
+
+namespace {
+
+__device__ inline cd gamma_star(int n, cd z, int* range_flag)
+{
+    double az = cabs_(z);
+    if (az <= (double)n + 0.5) {
+        cd term = mk(exp(-lgamma((double)n + 1.0)), 0.0);
+        cd sum = term;
+        for (int k = 1; k < 20000; ++k) {
+            term = term * z * (1.0 / (double)(n + k));
+            sum += term;
+            if (norm2(term) <= 1e-36 * norm2(sum)) break;
+            if (k == 19999) *range_flag = 1;
+        }
+        return cexp_(-z) * sum;
+    }
+    // inner = sum_{i=0}^{n-1} (n-1)!/(n-1-i)! z^{-i}
+    cd zi = cdiv(mk(1.0, 0.0), z);
+    cd t = mk(1.0, 0.0), s = mk(1.0, 0.0);
+    for (int i = 0; i < n - 1; ++i) {
+        t = t * zi * (double)(n - 1 - i);
+        s += t;
+    }
+    cd lz = clog_(z);
+    cd zn = cexp_(-(double)n * lz);
+    cd tail = cexp_(-z - lz - mk(lgamma((double)n), 0.0)) * s;
+    return zn - tail;
+}
+
+// sum over round trips for phi(-a-s) = e^{-lambda s} (the factor A e^{-ika}
+// is applied by the caller); row r, T_m = (r - mD) Delta
+__device__ cd delay_series(const Geom& g, cd lam, int64_t r, int* range_flag)
+{
+    const cd b = g.W - lam;
+    const double hg = 0.5 * g.Gamma;
+    const cd gmb = mk(hg, 0.0) - b;           // G/2 - b
+    const double lhg = log(hg);
+    cd sum = mk(0.0, 0.0);
+    for (int64_t m = 0; m * g.D < r; ++m) {
+        const int64_t q = r - m * g.D;
+        const double T = (double)q * g.Delta;
+        const cd z = b * T;
+        const cd eL = cexp_(-(lam * T));
+        if (m == 0) {
+            sum += eL * (T * gamma_star(1, z, range_flag));
+        } else {
+            const double lp = (double)(m - 1) * lhg + (double)m * log(T);
+            if (lp > 650.0) *range_flag = 1;
+            const double f1 = exp(lp) * T;
+            const double f2 = exp(lp - lgamma((double)m + 1.0));
+            sum += eL * (gmb * (f1 * gamma_star((int)m + 1, z, range_flag)));
+            sum -= f2 * cexp_(-(g.W * T));
+        }
+    }
+    return sqrt(hg) * sum;
+}
+
+// Eq. (9): emitter excited at t = 0, no incident photon
+__device__ cd stimulated(const Geom& g, int64_t r)
+{
+    const double hg = 0.5 * g.Gamma;
+    const cd w2a = cexp_(g.W * (2.0 * g.a));
+    cd s = mk(0.0, 0.0);
+    for (int64_t n = 0; n * g.D <= r; ++n) {
+        const double T = (double)(r - n * g.D) * g.Delta;
+        if (n == 0) { s += mk(1.0, 0.0); continue; }
+        // [(G/2) e^{2aW} T]^n / n!
+        const cd base = (hg * T) * w2a;
+        const cd lb = clog_(base);
+        s += cexp_((double)n * lb - mk(lgamma((double)n + 1.0), 0.0));
+    }
+    return cexp_(-(g.W * ((double)r * g.Delta))) * s;
+}
+
+// phi inside its support (x <= -a)
+__device__ inline cd phi_in(const Packet& pk, double x)
+{
+    switch (pk.incident) {
+    case FDTD_INC_PLANE: {
+        double s, c;
+        sincos(pk.k * x, &s, &c);
+        return mk(c, s);
+    }
+    case FDTD_INC_EXP1:
+    case FDTD_INC_EXP2: {
+        double amp = sqrt(pk.alpha * pk.Gamma) * exp(0.5 * pk.alpha * pk.Gamma * (x + pk.a));
+        double s, c;
+        sincos(pk.k * x, &s, &c);
+        return mk(-amp * s, amp * c);          // i amp e^{ikx}
+    }
+    default: {
+        double u = x - pk.x0, w = pk.width;
+        double amp = pow(2.0 * M_PI * w * w, -0.25) * exp(-u * u / (4.0 * w * w));
+        double s, c;
+        sincos(pk.k * u, &s, &c);
+        return mk(amp * c, amp * s);
+    }
+    }
+}
+
+// mass of |phi|^2 below y (y <= -a)
+__device__ inline double phi_mass_below(const Packet& pk, double y)
+{
+    switch (pk.incident) {
+    case FDTD_INC_GAUSS2: return 0.5 * erfc((pk.x0 - y) / (sqrt(2.0) * pk.width));
+    case FDTD_INC_EXP1:
+    case FDTD_INC_EXP2: return exp(pk.alpha * pk.Gamma * (y + pk.a));
+    default: return __builtin_nan("");
+    }
+}
+
+// phi on the grid, the drive per row, and row 0's share of int |psi|^2
+__global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > g.Nt) return;
+    b.Phi[q] = phi_in(pk, -g.a - (double)q * g.Delta);
+    cd d = mk(0.0, 0.0);
+    if (q >= 1) {
+        // t_c = (q - 1/2) Delta; phi(-a - t_c) - phi(a - t_c), the second
+        // inside the support only once t_c > 2a, i.e. q >= D + 1
+        d = phi_in(pk, -g.a - ((double)q - 0.5) * g.Delta);
+        if (q >= g.D + 1) d -= phi_in(pk, -g.a - ((double)(q - g.D) - 0.5) * g.Delta);
+        d = pk.c_drive * d;
+    }
+    b.Drv[q] = d;
+    // partial sums of row 0 (only column 0 can be non-zero there)
+    if (q < nblk) b.Ppart[q] = 0.0;
+}
+
+__global__ void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
+                    int nk, double k_lo, double hk)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > g.Nt) return;
+    int range_flag = 0;
+    cd E;
+    if (from_host) {
+        E = b.Ebuf[r];
+    } else if (pk.incident == FDTD_INC_EXP1) {
+        E = stimulated(g, r);
+    } else if (pk.incident == FDTD_INC_GAUSS2) {
+        // c(k) = (N w / sqrt(pi)) e^{-i k x0} e^{-w^2 (k-k0)^2}; each plane
+        // wave e^{ikx} (x <= -a) contributes e^{-ika} times its delay series
+        const double w = pk.width;
+        const double nrm = pow(2.0 * M_PI * w * w, -0.25) * w / sqrt(M_PI);
+        cd acc = mk(0.0, 0.0);
+        for (int i = 0; i < nk; ++i) {
+            const double kk = k_lo + (double)i * hk;
+            const double dk = kk - pk.k;
+            const double wt = hk * nrm * exp(-(w * dk) * (w * dk));
+            double s, c;
+            sincos(-kk * (pk.x0 + g.a), &s, &c);
+            const cd ser = delay_series(g, mk(0.0, kk), r, &range_flag);
+            acc += (wt * mk(c, s)) * ser;
+        }
+        E = acc;
+    } else {
+        // plane wave (A = 1) or exponential packet (A = i sqrt(alpha G))
+        cd lam = mk(0.0, pk.k);
+        cd A = mk(1.0, 0.0);
+        if (pk.incident == FDTD_INC_EXP2) {
+            lam = mk(0.5 * pk.alpha * pk.Gamma, pk.k);
+            A = mk(0.0, sqrt(pk.alpha * pk.Gamma));
+        }
+        double s, c;
+        sincos(-pk.k * g.a, &s, &c);
+        E = A * mk(c, s) * delay_series(g, lam, r, &range_flag);
+    }
+    cd Et = pk.c_ex * E;
+    b.Et[r] = Et;
+    const double t = (double)r * g.Delta;
+    b.Pex[r] = norm2(Et) * phi_mass_below(pk, -g.a - t);
+    if (range_flag) atomicOr(b.status, STATUS_GAMMA_RANGE);
+    if (!isfinite(Et.re) || !isfinite(Et.im)) atomicOr(b.status, STATUS_NONFINITE);
+    if (r == 0) {
+        // row 0: psi(x,0) = 0 for x > -a; column 0 carries c phi(-a) E(0)
+        cd v = b.Phi[0] * Et;
+        b.Ppart[0] = 0.5 * norm2(v);
+    }
+    (void)nblk;
+}
+
+__global__ void k_clear_status(int* st)
+{
+    if (threadIdx.x == 0) *st = 0;
+}
+
+__global__ void k_zero(cd* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = mk(0.0, 0.0);
+}
+
+}  // namespace
+
+// Node set of the plane-wave superposition for the Gaussian packet: range
+// k0 +- 6.5/w (weights below e^{-42}) and spacing h with 2 pi/h beyond both
+// the distance from the packet to -a and the distance a periodic image must
+// keep to the left of -a - T, each with a 13 w margin.
+static void gauss_nodes(const fdtd_ctx* c, int* nk, double* k_lo, double* hk)
+{
+    const double w = c->p.width;
+    const double T = (double)c->p.Nt * c->p.Delta;
+    const double d0 = -c->g.a - c->p.x0;
+    double L = d0 + 13.0 * w;
+    if (T - d0 + 13.0 * w > L) L = T - d0 + 13.0 * w;
+    const double h = 2.0 * M_PI / L;
+    const int half = (int)ceil(6.5 / w / h);
+    *nk = 2 * half + 1;
+    *k_lo = c->p.k - half * h;
+    *hk = h;
+}
+
+int launch_boundary(fdtd_ctx* c, int from_host_E)
+{
+    const int64_t n = c->g.Nt + 1;
+    const int th = 128;
+    const int64_t blocks = (n + th - 1) / th;
+    hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, c->stream, c->b.status);
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)blocks), dim3(th), 0, c->stream, c->g, c->pk, c->b, c->nblk);
+    int nk = 0;
+    double k_lo = 0.0, hk = 0.0;
+    if (c->p.incident == FDTD_INC_GAUSS2) gauss_nodes(c, &nk, &k_lo, &hk);
+    // small E-threads blocks: the work per row grows with r, so spread rows
+    hipLaunchKernelGGL(k_E, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, c->stream, c->g, c->pk, c->b,
+                       from_host_E, c->nblk, nk, k_lo, hk);
+    // row 0 of the ring is the initial condition (zero for x > -a)
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, c->g.C);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_clear(fdtd_ctx* c)
+{
+    const int64_t n = c->g.R * c->g.C;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, n);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}

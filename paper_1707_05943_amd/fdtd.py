@@ -1,0 +1,169 @@
+"""Python binding of the C ABI in include/fdtd.h (argument marshalling only).
+
+Every step of the march runs in the HIP library; this module allocates the
+device workspace with PyTorch, passes pointers and sizes, and copies results
+back.  There is no fallback: if the library is missing or cannot be loaded,
+`load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdtd.so")
+
+FDTD_ABI_VERSION = 1
+INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
+RO_ROW, RO_PE, RO_CHI, RO_E = 1, 2, 3, 4
+STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", -4: "FDTD_EDEVICE",
+          -5: "FDTD_ERANGE"}
+
+# every symbol include/fdtd.h declares
+EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_boundary_tables",
+           "fdtd_march", "fdtd_current_row", "fdtd_readout", "fdtd_sync", "fdtd_destroy",
+           "fdtd_strerror", "fdtd_last_error")
+
+
+class FdtdParams(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("struct_size", ctypes.c_uint32),
+                ("Nx", ctypes.c_int64), ("D", ctypes.c_int64), ("Nt", ctypes.c_int64),
+                ("Delta", ctypes.c_double), ("omega0", ctypes.c_double), ("Gamma", ctypes.c_double),
+                ("incident", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("k", ctypes.c_double), ("alpha", ctypes.c_double), ("x0", ctypes.c_double),
+                ("width", ctypes.c_double), ("phase", ctypes.c_double)]
+
+
+class FdtdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FdtdError(-4, f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    P = ctypes.POINTER(FdtdParams)
+    lib.fdtd_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdtd_init.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.fdtd_set_boundary.argtypes = [vp]
+    lib.fdtd_set_boundary_tables.argtypes = [vp, vp, i64]
+    lib.fdtd_march.argtypes = [vp, i64]
+    lib.fdtd_current_row.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.fdtd_readout.argtypes = [vp, i32, i64, vp, i64, i32]
+    lib.fdtd_sync.argtypes = [vp]
+    lib.fdtd_destroy.argtypes = [vp]
+    lib.fdtd_strerror.argtypes = [ctypes.c_int]
+    lib.fdtd_strerror.restype = ctypes.c_char_p
+    lib.fdtd_last_error.argtypes = [vp]
+    lib.fdtd_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def params(inst) -> FdtdParams:
+    d = inst if isinstance(inst, dict) else inst.as_dict()
+    return FdtdParams(abi_version=FDTD_ABI_VERSION, struct_size=ctypes.sizeof(FdtdParams),
+                      Nx=int(d["Nx"]), D=int(d["D"]), Nt=int(d["Nt"]), Delta=float(d["Delta"]),
+                      omega0=float(d["omega0"]), Gamma=float(d["Gamma"]), incident=int(d["incident"]),
+                      reserved0=0, k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
+                      x0=float(d.get("x0", 0.0)), width=float(d.get("width", 1.0)),
+                      phase=float(d.get("phase", 0.0)))
+
+
+def workspace_size(inst) -> int:
+    lib = load()
+    p = params(inst)
+    n = ctypes.c_size_t(0)
+    rc = lib.fdtd_workspace_size(ctypes.byref(p), ctypes.byref(n))
+    if rc:
+        raise FdtdError(rc, lib.fdtd_last_error(None).decode())
+    return int(n.value)
+
+
+class Solver:
+    """One instance of the march on one GPU (a context bound to a torch stream)."""
+
+    def __init__(self, inst, device: str = "cuda:0", stream=None):
+        import torch
+        self.lib = load()
+        self.inst = inst
+        self.p = params(inst)
+        self.device = torch.device(device)
+        self.torch = torch
+        nbytes = workspace_size(inst)
+        # 256-byte aligned workspace owned by this object (torch's allocator aligns to 512)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p(0)
+        rc = self.lib.fdtd_init(ctypes.byref(self.p), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc:
+            raise FdtdError(rc, self.lib.fdtd_last_error(None).decode())
+        self.ctx = ctx
+
+    def _check(self, rc):
+        if rc:
+            raise FdtdError(rc, self.lib.fdtd_last_error(self.ctx).decode())
+
+    def set_boundary(self, E: np.ndarray | None = None):
+        if E is None:
+            self._check(self.lib.fdtd_set_boundary(self.ctx))
+        else:
+            E = np.ascontiguousarray(E, dtype=np.complex128)
+            self._check(self.lib.fdtd_set_boundary_tables(self.ctx, E.ctypes.data_as(ctypes.c_void_p), E.size))
+        return self
+
+    def march(self, n_rows: int):
+        self._check(self.lib.fdtd_march(self.ctx, int(n_rows)))
+        return self
+
+    @property
+    def row(self) -> int:
+        r = ctypes.c_int64(0)
+        self._check(self.lib.fdtd_current_row(self.ctx, ctypes.byref(r)))
+        return int(r.value)
+
+    def _ro(self, what, arg, count, dtype):
+        out = np.empty(count, dtype=dtype)
+        self._check(self.lib.fdtd_readout(self.ctx, what, int(arg), out.ctypes.data_as(ctypes.c_void_p),
+                                          int(count), 0))
+        return out
+
+    def row_values(self, rho: int) -> np.ndarray:
+        return self._ro(RO_ROW, rho, self.p.Nx + 1, np.complex128)
+
+    def pe(self, count: int | None = None) -> np.ndarray:
+        return self._ro(RO_PE, 0, self.row + 1 if count is None else count, np.float64)
+
+    def chi(self, count: int) -> np.ndarray:
+        return self._ro(RO_CHI, 0, count, np.complex128)
+
+    def E(self) -> np.ndarray:
+        """the boundary table c E(t_r)"""
+        return self._ro(RO_E, 0, self.p.Nt + 1, np.complex128)
+
+    def sync(self):
+        self._check(self.lib.fdtd_sync(self.ctx))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.fdtd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

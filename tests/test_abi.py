@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every symbol include/fdtd.h declares;
+host-side validation works without a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1707_05943_amd import fdtd
+from paper_1707_05943_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtd_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(fdtd.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fdtd.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_params_struct_layout_matches_header():
+    # 3 x u32/u32 header + 3 int64 + 3 double + 2 int32 + 5 double
+    assert ctypes.sizeof(fdtd.FdtdParams) == 8 + 24 + 24 + 8 + 40
+
+
+def _bad(**kw):
+    d = W.small_gauss().as_dict()
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kw", [dict(D=7), dict(D=0), dict(Nx=100), dict(Delta=0.0), dict(Gamma=-1.0),
+                                dict(omega0=float("nan")), dict(incident=9), dict(width=0.0),
+                                dict(x0=1.0), dict(Nt=0)])
+def test_workspace_size_rejects_invalid_parameters(kw):
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.workspace_size(_bad(**kw))
+    assert e.value.code == -1
+
+
+def test_workspace_size_counts_the_ring():
+    inst = W.small_gauss()
+    n = fdtd.workspace_size(inst)
+    ring = (inst.D + 2) * (inst.Nx + 1) * 16
+    assert ring <= n < ring + 64 * (inst.Nt + 1) * 16 + (1 << 20)
+    big = W.large_gauss()
+    nb = fdtd.workspace_size(big)
+    assert nb >= (big.D + 2) * (big.Nx + 1) * 16            # ~42 GB ring
+    assert nb < 50 * 2**30
+
+
+def test_strerror_texts():
+    lib = fdtd.load()
+    assert lib.fdtd_strerror(0) == b"ok"
+    assert lib.fdtd_strerror(-2) == b"buffer too small"
