@@ -132,6 +132,12 @@ int fdtd_sync(fdtd_ctx *ctx);
 /* Free the context (not the workspace).  Accepts NULL. */
 int fdtd_destroy(fdtd_ctx *ctx);
 
+/* Text description of the work decomposition the library would use for
+ * these parameters (rows per launch, halo, workgroups of the strip and of
+ * the outgoing region, ring rows), written into buf (at most n bytes,
+ * NUL-terminated).  Host only; no device work. */
+int fdtd_describe(const fdtd_params *p, char *buf, size_t n);
+
 /* Static text for a status code; text of the last failure of ctx (or of the
  * last failed fdtd_init / fdtd_workspace_size when ctx is NULL). */
 const char *fdtd_strerror(int status);

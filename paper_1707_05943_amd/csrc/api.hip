@@ -45,6 +45,8 @@ static int halo_for(cd alpha)
     return h < 1.0 ? 1 : (int)h;
 }
 
+static int plan_for(const fdtd_params* p, Plan* P, char* why, size_t n);
+
 static int validate(const fdtd_params* p, char* why, size_t n)
 {
     if (!p) { snprintf(why, n, "params is NULL"); return FDTD_EINVAL; }
@@ -81,19 +83,26 @@ static int validate(const fdtd_params* p, char* why, size_t n)
                  cabs_(g.alpha), MAX_HALO);
         return FDTD_EINVAL;
     }
-    return FDTD_OK;
+    Plan P;
+    return plan_for(p, &P, why, n);
 }
 
 struct Layout {
-    int64_t ring, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, total;
+    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, total;
 };
 
-static Layout layout(const fdtd_params* p, int64_t nblk)
+// ring rows: the delay reaches D+1 rows back; the strip runs one block of T
+// rows ahead of the outgoing region and a launch may write up to 2T rows
+// past the oldest row it still reads
+static int64_t ring_rows(const fdtd_params* p, const Plan& P) { return p->D + 2 * (int64_t)P.T + 2; }
+
+static Layout layout(const fdtd_params* p, const Plan& P)
 {
     Layout L;
-    const int64_t C = p->Nx + 1, R = p->D + 2, n = p->Nt + 1;
+    const int64_t C = p->Nx + 1, R = ring_rows(p, P), n = p->Nt + 1, nblk = P.nwg;
     int64_t off = 0;
     L.ring = off; off += align256(R * C * 16);
+    L.Md = off; off += align256(R * (p->D + 1) * 16);
     L.Et = off; off += align256(n * 16);
     L.Phi = off; off += align256(n * 16);
     L.Drv = off; off += align256(n * 16);
@@ -107,7 +116,12 @@ static Layout layout(const fdtd_params* p, int64_t nblk)
     return L;
 }
 
-static int64_t blocks_per_row(const fdtd_params* p) { return (p->Nx + MARCH_TX - 1) / MARCH_TX; }
+static int plan_for(const fdtd_params* p, Plan* P, char* why, size_t n)
+{
+    Geom g;
+    coefficients(p, &g);
+    return make_plan(p, halo_for(g.alpha), P, why, n);
+}
 
 extern "C" {
 
@@ -117,7 +131,9 @@ int fdtd_workspace_size(const fdtd_params* p, size_t* bytes)
     int rc = validate(p, why, sizeof why);
     if (rc) return fail(nullptr, rc, "%s", why);
     if (!bytes) return fail(nullptr, FDTD_EINVAL, "bytes is NULL");
-    *bytes = (size_t)layout(p, blocks_per_row(p)).total;
+    Plan P;
+    plan_for(p, &P, why, sizeof why);
+    *bytes = (size_t)layout(p, P).total;
     return FDTD_OK;
 }
 
@@ -128,8 +144,10 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     if (rc) return fail(nullptr, rc, "%s", why);
     if (!out) return fail(nullptr, FDTD_EINVAL, "out is NULL");
     *out = nullptr;
-    const int64_t nblk = blocks_per_row(p);
-    Layout L = layout(p, nblk);
+    Plan P;
+    plan_for(p, &P, why, sizeof why);
+    const int64_t nblk = P.nwg;
+    Layout L = layout(p, P);
     if (!d_workspace || bytes < (size_t)L.total)
         return fail(nullptr, FDTD_ESIZE, "workspace of %zu bytes is smaller than the %lld needed", bytes,
                     (long long)L.total);
@@ -140,8 +158,9 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     c->p = *p;
     c->stream = (hipStream_t)hip_stream;
     c->nblk = nblk;
+    c->plan = P;
     Geom& g = c->g;
-    g.Nx = p->Nx; g.D = p->D; g.Nt = p->Nt; g.C = p->Nx + 1; g.R = p->D + 2;
+    g.Nx = p->Nx; g.D = p->D; g.Nt = p->Nt; g.C = p->Nx + 1; g.R = ring_rows(p, P); g.Mc = p->D + 1;
     g.Delta = p->Delta; g.a = 0.5 * (double)p->D * p->Delta; g.Gamma = p->Gamma;
     coefficients(p, &g);
     g.halo = halo_for(g.alpha);
@@ -161,6 +180,7 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     char* base = (char*)d_workspace;
     Bufs& b = c->b;
     b.ring = (cd*)(base + L.ring);
+    b.Md = (cd*)(base + L.Md);
     b.Et = (cd*)(base + L.Et);
     b.Phi = (cd*)(base + L.Phi);
     b.Drv = (cd*)(base + L.Drv);
@@ -171,6 +191,7 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     b.Ebuf = (cd*)(base + L.Ebuf);
     b.status = (int*)(base + L.status);
     c->row = -1;
+    c->strip_row = -1;
     c->boundary_ready = 0;
     rc = launch_clear(c);
     if (rc) { free(c); return fail(nullptr, rc, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError())); }
@@ -197,6 +218,7 @@ int fdtd_set_boundary(fdtd_ctx* c)
     rc = check_status(c);
     if (rc) return rc;
     c->row = 0;
+    c->strip_row = 0;
     c->boundary_ready = 1;
     return FDTD_OK;
 }
@@ -212,7 +234,36 @@ int fdtd_set_boundary_tables(fdtd_ctx* c, const double* h_E, int64_t n)
     rc = check_status(c);
     if (rc) return rc;
     c->row = 0;
+    c->strip_row = 0;
     c->boundary_ready = 1;
+    return FDTD_OK;
+}
+
+// Launch schedule.  Rows are grouped in blocks [1 + kT, (k+1)T].  A launch
+// marches the outgoing region over (a prefix of) one block and the strip
+// over the next block.  A march that stopped inside a block resumes from the
+// block's first row, so every row is computed from the same block start
+// whatever the call boundaries (the results are bitwise the same).
+static int march_to(fdtd_ctx* c, int64_t target)
+{
+    const int64_t T = c->plan.T, Nt = c->p.Nt;
+    while (c->row < target) {
+        const int64_t m0 = 1 + T * (c->row / T);
+        const int64_t m1 = (m0 + T - 1 < target) ? m0 + T - 1 : target;
+        int64_t s0 = c->strip_row + 1, s1 = -1;
+        if (s0 <= Nt && s0 <= m0 + T) s1 = (s0 + T - 1 < Nt) ? s0 + T - 1 : Nt;
+        if (c->strip_row < m1) {
+            // the strip must hold every row this block reads: march it alone first
+            int rc = launch_block(c, 1, 0, s0, s1);
+            if (rc) return rc;
+            c->strip_row = s1;
+            continue;
+        }
+        int rc = launch_block(c, m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
+        if (rc) return rc;
+        c->row = m1;
+        if (s1 >= s0) c->strip_row = s1;
+    }
     return FDTD_OK;
 }
 
@@ -223,9 +274,8 @@ int fdtd_march(fdtd_ctx* c, int64_t n_rows)
     if (n_rows < 0) return fail(c, FDTD_EINVAL, "n_rows < 0");
     if (c->row + n_rows > c->p.Nt) return fail(c, FDTD_ESTATE, "march past Nt = %lld", (long long)c->p.Nt);
     if (n_rows == 0) return FDTD_OK;
-    int rc = launch_march_rows(c, c->row + 1, c->row + n_rows);
+    int rc = march_to(c, c->row + n_rows);
     if (rc) return fail(c, rc, "march launch failed: %s", hipGetErrorString(hipGetLastError()));
-    c->row += n_rows;
     return FDTD_OK;
 }
 
@@ -297,6 +347,27 @@ int fdtd_sync(fdtd_ctx* c)
 int fdtd_destroy(fdtd_ctx* c)
 {
     free(c);
+    return FDTD_OK;
+}
+
+int fdtd_describe(const fdtd_params* p, char* buf, size_t n)
+{
+    char why[256];
+    int rc = validate(p, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    if (!buf || n == 0) return fail(nullptr, FDTD_EINVAL, "buf is NULL");
+    Plan P;
+    plan_for(p, &P, why, sizeof why);
+    Geom g;
+    coefficients(p, &g);
+    snprintf(buf, n,
+             "{\"T\": %d, \"H\": %d, \"hmax\": %d, \"cone_mode\": %d, \"Gs\": %d, \"Gm\": %d, \"Gn\": %d, "
+             "\"strip_w\": %lld, \"near_w\": %lld, \"far_w\": %lld, \"near_end\": %lld, \"cone_L0\": %lld, "
+             "\"nwg\": %d, \"nb\": %d, "
+             "\"ring_rows\": %lld, \"alpha_abs\": %.6g, \"threads\": %d, \"cols_per_thread\": %d}",
+             P.T, P.H, P.hmax, P.cone_mode, P.Gs, P.Gm, P.Gn, (long long)P.strip_w, (long long)P.near_w,
+             (long long)P.far_w, (long long)P.near_end,
+             (long long)P.cone_L0, P.nwg, P.nb, (long long)ring_rows(p, P), cabs_(g.alpha), BM_THREADS, BM_K);
     return FDTD_OK;
 }
 

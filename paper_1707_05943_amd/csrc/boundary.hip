@@ -221,6 +221,14 @@ __global__ void k_clear_status(int* st)
     if (threadIdx.x == 0) *st = 0;
 }
 
+// row 0 of the strip in its diagonal copy: psi(c, 0) = 0 sits at row D - c
+__global__ void k_md_row0(Geom g, Bufs b)
+{
+    int64_t c = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > g.D) return;
+    b.Md[(g.D - c) * g.Mc + c] = mk(0.0, 0.0);
+}
+
 __global__ void k_zero(cd* p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -262,6 +270,7 @@ int launch_boundary(fdtd_ctx* c, int from_host_E)
                        from_host_E, c->nblk, nk, k_lo, hk);
     // row 0 of the ring is the initial condition (zero for x > -a)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, c->g.C);
+    hipLaunchKernelGGL(k_md_row0, dim3((unsigned)((c->g.D + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 

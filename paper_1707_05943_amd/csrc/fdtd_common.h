@@ -50,7 +50,8 @@ __host__ __device__ inline cd clog_(cd z) { return cd{log(hypot(z.re, z.im)), at
 struct Geom {
     int64_t Nx, D, Nt;
     int64_t C;          // columns per ring row = Nx + 1 (row pitch in elements)
-    int64_t R;          // ring rows
+    int64_t R;          // ring rows (also the rows of the diagonal copy of the strip)
+    int64_t Mc;         // row pitch of the diagonal copy of the strip = D + 1
     double Delta, a, Gamma;
     cd W;               // i omega0 + Gamma/2
     cd alpha;           // coefficient of psi(j-1, r) in the solved square
@@ -70,6 +71,7 @@ struct Packet {           // incident packet phi and the exact-solution prefacto
 // device pointers carved from the caller's workspace
 struct Bufs {
     cd* ring;        // R x C
+    cd* Md;          // the strip along anti-diagonals: psi(c, rho) at row (rho - c + D) mod R, column c (R x Mc)
     cd* Et;          // c_ex E(t_r), r = 0..Nt
     cd* Phi;         // phi(-a - q Delta), q = 0..Nt
     cd* Drv;         // drive per row, r = 0..Nt (r = 0 unused)
@@ -81,15 +83,42 @@ struct Bufs {
     int* status;     // device error flags
 };
 
+// Work decomposition of the blocked march (fixed per context).
+// Rows are marched in blocks of T; one launch computes one block of the
+// outgoing region (columns D+1..Nx) and, one block ahead, the next block of
+// the mirror strip (columns 1..D).  Every workgroup computes its columns for
+// T rows from data of earlier launches only: a workgroup whose left
+// neighbour is marched in the same launch recomputes a trapezoidal halo
+// that starts (H+1)T-1 columns to its left and shrinks by H+1 per row.
+struct Plan {
+    int T;               // rows per block
+    int H;               // columns of the within-row recurrence kept (|alpha|^H < 2^-60)
+    int hmax;            // halo at a block's first row: (H+1)T - 1
+    int cone_mode;       // 0: one strip workgroup marches the whole strip exactly;
+                         // 1: several strip workgroups, the first also computes a cone at the strip's right end
+    int Gs, Gm;          // strip and outgoing-region workgroups
+    int Gn;              // of the Gm, those of the near part D+1..near_end (mirror reads)
+    int64_t strip_w;     // strip columns per strip workgroup (the last one takes the rest)
+    int64_t near_w;      // columns per near workgroup (the last one takes the rest)
+    int64_t far_w;       // columns per far workgroup (the last one takes the rest)
+    int64_t near_end;    // last column of the near part (>= 2D + hmax, so far halos hold no mirror reads)
+    int64_t cone_L0;     // cone width at a block's first row
+    int64_t win_lo;      // first strip column kept in the LDS window of the current block
+    int nwg;             // Gs + Gm
+    int nb;              // launched blocks (a multiple of 8, >= nwg)
+};
+
 struct fdtd_ctx {
     fdtd_params p;
     Geom g;
     Packet pk;
     Bufs b;
+    Plan plan;
     hipStream_t stream;
-    int64_t row;          // last solved row
+    int64_t row;          // last solved row of the whole grid
+    int64_t strip_row;    // last strip row marched (>= row)
     int boundary_ready;
-    int64_t nblk;         // blocks per row of the march kernel
+    int64_t nblk;         // per-row partial sums of |psi|^2 (one per workgroup)
     char err[512];
 };
 
@@ -97,13 +126,18 @@ enum { STATUS_GAMMA_RANGE = 1, STATUS_NONFINITE = 2 };
 
 // launch helpers implemented in the .hip files
 int launch_boundary(fdtd_ctx* c, int from_host_E);
-int launch_march_rows(fdtd_ctx* c, int64_t r0, int64_t r1);
 int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst);
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst);
 int launch_clear(fdtd_ctx* c);
 
-constexpr int MARCH_THREADS = 256;
-constexpr int MARCH_COLS_PER_THREAD = 4;
-constexpr int MARCH_TX = MARCH_THREADS * MARCH_COLS_PER_THREAD;   // columns per block
 constexpr int MAX_HALO = 64;
+
+// blocked march: threads per workgroup and columns per thread
+constexpr int BM_THREADS = 512;
+constexpr int BM_K = 3;
+constexpr int BM_CAP = BM_THREADS * BM_K;      // columns a workgroup can hold in one row
+constexpr int BM_TMAX = 32;                    // largest block of rows (LDS window is BM_TMAX x BM_TMAX)
+
+int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n);
+int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1);

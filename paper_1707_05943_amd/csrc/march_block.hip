@@ -1,0 +1,595 @@
+// The blocked march of Eq. (1).
+//
+// Update of one square (Eq. 3 for the line-1 terms, Eq. 4 bars for the
+// source terms, the drive at the square's centre):
+//
+//   psi(j, r) = alpha psi(j-1, r) + beta(j, r)
+//   beta      = cA psi(j-1, r-1) + cB psi(j, r-1) + cinv S
+//   S         = (G/8)[psi(j-1-D, r-1-D) + psi(j-D, r-1-D) + psi(j-1-D, r-D) + psi(j-D, r-D)]   (r-1 >= D)
+//               - (G/2)[bar(-j, r-j) - bar(D-j, r-j)]                                        (r-j >= 0)
+//               - (G/2)[bar(2D-j, r-j+D) - bar(D-j, r-j+D)]                                  (j > D, r-j+D >= 0)
+//               + c_drive phi(x_j - t_r)[phi(-a - t_c) - phi(a - t_c)]
+//
+// with bar(i, rho) = [psi(i, rho) + psi(i+1, rho)]/2 and psi at columns <= 0
+// the exact solution Phi[rho - i] Et[rho].  In the exact parts this gives
+//   bar(-j, r-j)       = Et[r-j] (Phi[r] + Phi[r-1]) / 2
+//   bar(D-j, r-j)      = Et[r-j] (Phi[r-D] + Phi[r-D-1]) / 2           (j > D)
+//   bar(D-j, r-j+D)    = Et[r-j+D] (Phi[r] + Phi[r-1]) / 2            (j > D)
+//   bar(2D-j, r-j+D)   = Et[r-j+D] (Phi[r-D] + Phi[r-D-1]) / 2        (j > 2D)
+// while the strip (j <= D) and the near outgoing region (D < j <= 2D) read
+// marched values along the anti-diagonal rho - i = r - D ("mirror" reads).
+//
+// Decomposition.  One launch marches a block of T rows of the outgoing
+// region (columns D+1..Nx) and, one block ahead, a block of the strip
+// (columns 1..D), which depends on nothing to its right.  Each workgroup
+// owns a column range and marches it through the block using only values
+// written by earlier launches:
+//  * the outgoing region's first workgroup takes psi(D, r) from the strip
+//    (already marched), so its within-row recurrence is exact;
+//  * the strip's first workgroup starts from the exact column 0;
+//  * every other workgroup recomputes a trapezoidal halo: at block row tau it
+//    evaluates columns from c0 - (H+1)(T - tau) + 1.  Each row the halo loses
+//    H+1 columns -- one to the square's left corner, H to the recurrence
+//    psi = alpha psi_left + beta, whose terms beyond H columns are below
+//    |alpha|^H < 2^-60 relative -- so the owned columns are exact to that
+//    bound at every row;
+//  * mirror reads of the strip at lags below T (only columns j < T do this)
+//    come from a window in LDS that the strip's first workgroup fills from a
+//    cone of columns at the strip's right end, computed the same way.
+// The kernel boundary between launches makes every write of a launch
+// visible to the next one; no flags or fences are needed.
+
+#include <string.h>
+
+#include "fdtd_common.h"
+
+namespace {
+
+constexpr int NT = BM_THREADS;
+constexpr int K = BM_K;
+constexpr int NW = NT / 64;
+constexpr int TBL = BM_CAP + BM_TMAX;      // LDS table entries: indexes r - j over one block
+
+__device__ inline cd zero() { return mk(0.0, 0.0); }
+__device__ inline int64_t dec_slot(int64_t s, int64_t R) { return s == 0 ? R - 1 : s - 1; }
+__device__ inline int64_t inc_slot(int64_t s, int64_t R) { return s + 1 == R ? 0 : s + 1; }
+__device__ inline int64_t slot_of(int64_t q, int64_t R) { return q % R; }
+
+__device__ inline cd phi_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Phi[q] : zero(); }
+__device__ inline cd et_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Et[q] : zero(); }
+
+// psi at column i of row rho, given rho's ring slot: zero before t = 0, the
+// exact solution at columns <= 0, the ring otherwise
+__device__ inline cd rd_slot(const Geom& g, const Bufs& b, int64_t i, int64_t rho, int64_t slot)
+{
+    if (rho < 0) return zero();
+    if (i <= 0) return b.Phi[rho - i] * b.Et[rho];
+    return b.ring[slot * g.C + i];
+}
+
+__device__ inline cd rd(const Geom& g, const Bufs& b, int64_t i, int64_t rho)
+{
+    if (rho < 0) return zero();
+    return rd_slot(g, b, i, rho, slot_of(rho, g.R));
+}
+
+// cross-lane moves with DPP (GFX9 encodings); lanes without a source get 0
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long bits = __double_as_longlong(v);
+    int lo = (int)(unsigned)(bits & 0xffffffffLL), hi = (int)(bits >> 32);
+    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL, int RM>
+__device__ __forceinline__ cd dpp_cd(cd v) { return mk(dpp_f64<CTRL, RM>(v.re), dpp_f64<CTRL, RM>(v.im)); }
+
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
+
+// Powers of alpha for the scan of psi = alpha psi_left + beta over a wave:
+// a[i] = alpha^i (i <= K), s[k] = alpha^(K 2^k) (k < 4), and per lane l
+// m15 = alpha^(K((l mod 32) - 15)), m31 = alpha^(K(l - 31)), lp = alpha^(K l),
+// m64 = alpha^(64 K).
+struct Pow {
+    cd a[K + 1];
+    cd s[4];
+    cd m15, m31, lp, m64;
+};
+
+__device__ inline cd cpow_u(cd x, int e)
+{
+    cd r = mk(1.0, 0.0);
+    while (e > 0) {
+        if (e & 1) r = r * x;
+        x = x * x;
+        e >>= 1;
+    }
+    return r;
+}
+
+__device__ inline Pow make_pow(cd al)
+{
+    Pow p;
+    p.a[0] = mk(1.0, 0.0);
+    for (int i = 1; i <= K; ++i) p.a[i] = p.a[i - 1] * al;
+    cd m = p.a[K];
+    for (int k = 0; k < 4; ++k) { p.s[k] = m; m = m * m; }
+    const int lane = threadIdx.x & 63;
+    const int l32 = lane & 31;
+    p.m15 = (l32 >= 16) ? cpow_u(p.a[K], l32 - 15) : mk(0.0, 0.0);
+    p.m31 = (lane >= 32) ? cpow_u(p.a[K], lane - 31) : mk(0.0, 0.0);
+    p.lp = cpow_u(p.a[K], lane);
+    p.m64 = cpow_u(p.a[K], 64);
+    return p;
+}
+
+// inclusive scan over a wave of x_l = v_l + alpha^K x_{l-1}
+__device__ __forceinline__ cd wave_scan(cd x, const Pow& P)
+{
+    x += P.s[0] * dpp_cd<DPP_ROW_SHR1, 0xF>(x);
+    x += P.s[1] * dpp_cd<DPP_ROW_SHR2, 0xF>(x);
+    x += P.s[2] * dpp_cd<DPP_ROW_SHR4, 0xF>(x);
+    x += P.s[3] * dpp_cd<DPP_ROW_SHR8, 0xF>(x);
+    x += P.m15 * dpp_cd<DPP_ROW_BCAST15, 0xA>(x);
+    x += P.m31 * dpp_cd<DPP_ROW_BCAST31, 0xC>(x);
+    return x;
+}
+
+// sum over a wave, complete in lane 63
+__device__ __forceinline__ double wave_sum63(double v)
+{
+    v += dpp_f64<DPP_ROW_SHR1, 0xF>(v);
+    v += dpp_f64<DPP_ROW_SHR2, 0xF>(v);
+    v += dpp_f64<DPP_ROW_SHR4, 0xF>(v);
+    v += dpp_f64<DPP_ROW_SHR8, 0xF>(v);
+    v += dpp_f64<DPP_ROW_BCAST15, 0xA>(v);
+    v += dpp_f64<DPP_ROW_BCAST31, 0xC>(v);
+    return v;
+}
+
+struct Range {
+    int64_t lo;      // column of thread 0's first value
+    int64_t hi;      // one past the last column
+    int64_t own_lo;  // first column written to the ring (own_lo >= hi: none)
+    int exact;       // the value left of `lo` is exact (from memory) in every row
+};
+
+struct Win {                     // the strip's right end for the rows of the current strip block
+    cd (*w)[BM_TMAX];
+    int64_t lo;                  // first column held
+    int64_t row0;                // first row held (the block's first row)
+    int on;                      // mirror reads of rows >= row0 go to the window
+};
+
+// Per-row values shared by the whole workgroup (computed once per block)
+struct RowInfo {
+    int64_t slot;                // ring slot of row r; also the row of diagonal r - D in Md
+    int64_t slot_m1;             // ring slot of row r-1; also the row of diagonal r - D - 1 in Md
+    int64_t slot_pf;             // ring slot of row r+1-D (-1 if that row is before t = 0)
+    cd half_pr;                  // (Phi[r] + Phi[r-1]) / 2
+    cd half_qr;                  // (Phi[r-D] + Phi[r-D-1]) / 2
+    cd drv;                      // drive factor of row r
+    int delay_on;                // r - 1 >= D
+};
+
+// Per-thread state of one column range through a block.
+struct Lane {
+    cd up[K];                    // psi(j, r-1) for the thread's columns
+    cd upL;                      // psi(j0-1, r-1)
+    cd dA[K + 1];                // row r-1-D at columns j0-1-D .. j0+K-1-D
+    cd dB[K + 1];                // row r-D at the same columns
+    int64_t sd;                  // row of Md holding diagonal r - j0 (the thread's first column)
+};
+
+// delay values of row rho (ring slot `sl`, or sl < 0 before t = 0)
+__device__ __forceinline__ void load_delay_row(const Geom& g, const Bufs& b, int64_t j0, int64_t rho, int64_t sl,
+                                               cd* out)
+{
+    if (sl < 0) {
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) out[i] = zero();
+        return;
+    }
+    const cd* row = b.ring + sl * g.C;
+    #pragma unroll
+    for (int i = 0; i <= K; ++i) {
+        const int64_t c = j0 - 1 - g.D + i;
+        out[i] = (c <= 0) ? b.Phi[rho - c] * b.Et[rho] : ((c <= g.Nx) ? row[c] : zero());
+    }
+}
+
+// One row of one column range.
+//  FAR: every column of the range lies beyond 2D, where all source terms are
+//       exact; the tables dE[q] = Et[q] - Et[q+D] and F[q] = Phi[q] (q = r - j)
+//       come from LDS.
+//  otherwise: the generic update; mirror reads come from the diagonal copy
+//       Md (contiguous along the row) or, for the strip's first workgroup and
+//       rows of the current block, from the LDS window.
+// Returns this thread's share of sum |psi|^2 over the owned columns.
+template <bool FAR>
+__device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win& W, const Pow& P, const Range& R,
+                                         Lane& L, cd (*wave_tot)[NW], const cd* tblE, const cd* tblF, int64_t qa,
+                                         const RowInfo& ri, int64_t r, int64_t rb, int64_t act_lo, int par,
+                                         int write_ring, int write_win, int write_md)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t j0 = R.lo + (int64_t)tid * K;
+    const int64_t D = g.D;
+    const int64_t jmax = (R.hi - 1 < g.Nx) ? R.hi - 1 : g.Nx;
+    const int any = (j0 + K - 1 >= act_lo) && (j0 <= jmax);
+    const double g8 = 0.125 * g.Gamma, g2 = 0.5 * g.Gamma;
+
+    // prefetch the delay row of the next row
+    cd nx[K + 1];
+    if (any && r + 1 <= rb) load_delay_row(g, b, j0, r + 1 - D, ri.slot_pf, nx);
+
+    cd u[K];
+    if (any) {
+        if (FAR) {
+            const cd kr = (-g2) * (ri.half_pr - ri.half_qr);
+            #pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int64_t j = j0 + i;
+                const cd left = (i == 0) ? L.upL : L.up[i - 1];
+                cd S = zero();
+                if (ri.delay_on) S = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
+                const int64_t t = r - j - qa;
+                S += kr * tblE[t] + ri.drv * tblF[t];
+                cd v = g.cA * left + g.cB * L.up[i] + g.cinv * S;
+                u[i] = (j >= act_lo && j <= jmax) ? v : zero();
+            }
+        } else {
+            const cd* mdA = b.Md + ri.slot * g.Mc;       // diagonal r - D
+            const cd* mdB = b.Md + ri.slot_m1 * g.Mc;    // diagonal r - D - 1
+            #pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int64_t j = j0 + i;
+                const cd left = (i == 0) ? L.upL : L.up[i - 1];
+                if (!(j >= act_lo && j <= jmax)) { u[i] = zero(); continue; }
+                cd S = zero();
+                if (ri.delay_on) S = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
+                cd src = zero();
+                const int64_t q = r - j;
+                if (q >= 0) {
+                    const cd et = b.Et[q];
+                    cd mir;
+                    if (j <= D) {
+                        // bar(D-j, r-j): psi(D-j, q) on diagonal r-D, psi(D-j+1, q) on r-D-1
+                        const int inwin = W.on && q >= W.row0;
+                        cd m0, m1;
+                        if (j == D) m0 = b.Phi[q] * b.Et[q];
+                        else m0 = inwin ? W.w[q - W.row0][D - j - W.lo] : mdA[D - j];
+                        m1 = inwin ? W.w[q - W.row0][D - j + 1 - W.lo] : mdB[D - j + 1];
+                        mir = 0.5 * (m0 + m1);
+                    } else {
+                        mir = et * ri.half_qr;
+                    }
+                    src = et * ri.half_pr - mir;
+                    S += ri.drv * b.Phi[q];
+                }
+                if (j > D) {
+                    const int64_t q2 = q + D;
+                    if (q2 >= 0) {
+                        const cd et2 = b.Et[q2];
+                        cd mir2;
+                        if (j <= 2 * D) {
+                            // bar(2D-j, r-j+D): diagonals r-D and r-D-1 again
+                            const cd m0 = (j == 2 * D) ? b.Phi[q2] * b.Et[q2] : mdA[2 * D - j];
+                            mir2 = 0.5 * (m0 + mdB[2 * D - j + 1]);
+                        } else {
+                            mir2 = et2 * ri.half_qr;
+                        }
+                        src += mir2 - et2 * ri.half_pr;
+                    }
+                }
+                S -= g2 * src;
+                u[i] = g.cA * left + g.cB * L.up[i] + g.cinv * S;
+            }
+        }
+        #pragma unroll
+        for (int i = 1; i < K; ++i) u[i] = g.alpha * u[i - 1] + u[i];
+    } else {
+        #pragma unroll
+        for (int i = 0; i < K; ++i) u[i] = zero();
+    }
+
+    // carry into the range
+    cd carry0 = zero();
+    if (R.exact && tid == 0) {
+        const int64_t c = R.lo - 1;
+        carry0 = (c <= 0) ? b.Phi[r - c] * b.Et[r] : b.ring[ri.slot * g.C + c];
+    }
+
+    // x_t = u_last + alpha^K x_{t-1}: inclusive scan over the threads
+    cd x = u[K - 1];
+    if (tid == 0) x += P.a[K] * carry0;
+    x = wave_scan(x, P);
+    if (lane == 63) wave_tot[par][wv] = x;
+    const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
+    __syncthreads();
+    cd wcarry = zero();
+    for (int w2 = 0; w2 < wv; ++w2) wcarry = P.m64 * wcarry + wave_tot[par][w2];
+    // the value just left of this thread's first column
+    cd cin = prevx + P.lp * wcarry;
+    if (tid == 0) cin = carry0;
+
+    double pe = 0.0;
+    if (any) {
+        cd* row = b.ring + ri.slot * g.C;
+        int64_t sd = L.sd;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const int act = (j >= act_lo && j <= jmax);
+            const cd v = act ? u[i] + P.a[i + 1] * cin : zero();
+            u[i] = v;
+            if (act && j >= R.own_lo) {
+                if (write_ring) row[j] = v;
+                if (write_md) b.Md[sd * g.Mc + j] = v;
+                const double m2 = norm2(v);
+                pe += (j == g.Nx) ? 0.5 * m2 : m2;
+            }
+            if (write_win && act && j >= W.lo && j <= D) W.w[r - W.row0][j - W.lo] = v;
+            sd = dec_slot(sd, g.R);
+        }
+        // advance: psi(j0-1, r) is the carry that entered this thread
+        L.upL = cin;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) L.up[i] = u[i];
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) { L.dA[i] = L.dB[i]; L.dB[i] = nx[i]; }
+        L.sd = inc_slot(L.sd, g.R);
+    }
+    return pe;
+}
+
+__device__ inline int64_t slot_or_neg(int64_t rho, int64_t R) { return rho < 0 ? -1 : rho % R; }
+
+// the block's base row (row r0-1) and the delay rows of its first row
+__device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Range& R, Lane& L, int64_t r0)
+{
+    const int tid = threadIdx.x;
+    const int64_t j0 = R.lo + (int64_t)tid * K;
+    #pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t j = j0 + i;
+        L.up[i] = (j <= g.Nx && j < R.hi) ? rd(g, b, j, r0 - 1) : zero();
+    }
+    L.upL = (j0 - 1 <= g.Nx) ? rd(g, b, j0 - 1, r0 - 1) : zero();
+    const int64_t rA = r0 - 1 - g.D, rB = r0 - g.D;
+    load_delay_row(g, b, j0, rA, slot_or_neg(rA, g.R), L.dA);
+    load_delay_row(g, b, j0, rB, slot_or_neg(rB, g.R), L.dB);
+    const int64_t d = r0 - j0 + g.D;                    // diagonal r0 - j0, offset by D
+    L.sd = ((d % g.R) + g.R) % g.R;
+}
+
+__global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
+                                                       int64_t s0, int64_t s1)
+{
+    __shared__ cd wave_tot[2][NW];
+    __shared__ double pe_lds[BM_TMAX][NW];
+    __shared__ cd win[BM_TMAX][BM_TMAX];
+    __shared__ cd tblE[TBL];
+    __shared__ cd tblF[TBL];
+    __shared__ RowInfo rinfo[BM_TMAX];
+
+    const int bid = blockIdx.x;
+    const int w = (bid % 8) * (P.nb / 8) + bid / 8;     // neighbouring column ranges share an XCD
+    if (w >= P.nwg) return;
+    const int is_strip = w < P.Gs;
+    const int64_t ra = is_strip ? s0 : m0;
+    const int64_t rb = is_strip ? s1 : m1;
+    if (rb < ra) return;
+
+    const int64_t D = g.D;
+    Range R;
+    if (is_strip) {
+        const int64_t c0 = 1 + (int64_t)w * P.strip_w;
+        const int64_t c1 = (w == P.Gs - 1) ? D + 1 : c0 + P.strip_w;
+        R.exact = (w == 0);
+        R.lo = R.exact ? c0 : c0 - P.hmax;
+        R.hi = c1;
+        R.own_lo = c0;
+    } else {
+        const int m = w - P.Gs;
+        int64_t c0, c1;
+        if (m < P.Gn) {
+            c0 = D + 1 + (int64_t)m * P.near_w;
+            c1 = (m == P.Gn - 1) ? P.near_end + 1 : c0 + P.near_w;
+        } else {
+            const int f = m - P.Gn;
+            c0 = P.near_end + 1 + (int64_t)f * P.far_w;
+            c1 = (m == P.Gm - 1) ? g.Nx + 1 : c0 + P.far_w;
+        }
+        R.exact = (m == 0);
+        R.lo = R.exact ? c0 : c0 - P.hmax;
+        R.hi = c1;
+        R.own_lo = c0;
+    }
+    const int H1 = P.H + 1;
+    const Pow pw = make_pow(g.alpha);
+    const int far = (!is_strip) && (R.lo > 2 * D);
+    const int nrows = (int)(rb - ra + 1);
+
+    // per-row values of this block
+    if (threadIdx.x < nrows) {
+        const int64_t r = ra + threadIdx.x;
+        RowInfo ri;
+        ri.slot = r % g.R;
+        ri.slot_m1 = (r - 1) % g.R;
+        ri.slot_pf = slot_or_neg(r + 1 - D, g.R);
+        ri.half_pr = 0.5 * (phi_at(b, r) + phi_at(b, r - 1));
+        ri.half_qr = 0.5 * (phi_at(b, r - D) + phi_at(b, r - D - 1));
+        ri.drv = b.Drv[r];
+        ri.delay_on = (r - 1 >= D);
+        rinfo[threadIdx.x] = ri;
+    }
+    // the tables of the far region for this block: q = r - j in [qa, qb]
+    const int64_t qa = ra - (R.hi - 1);
+    if (far) {
+        const int64_t n = (R.hi - R.lo) + (rb - ra);
+        for (int64_t t = threadIdx.x; t <= n; t += NT) {
+            const int64_t q = qa + t;
+            tblE[t] = et_at(b, q) - et_at(b, q + D);
+            tblF[t] = phi_at(b, q);
+        }
+    }
+    __syncthreads();
+
+    Win W;
+    W.w = win;
+    W.lo = P.win_lo;
+    W.row0 = ra;
+    W.on = (is_strip && w == 0);
+    const int write_win = W.on && (P.cone_mode == 0);
+    const int cone = W.on && (P.cone_mode == 1);
+
+    if (cone) {
+        // the cone at the strip's right end, for every row of the block but
+        // the last: fills the window before the strip's own columns need it
+        Range C;
+        C.lo = D + 1 - P.cone_L0;
+        C.hi = D + 1;
+        C.own_lo = D + 1;                        // nothing owned
+        C.exact = 0;
+        Win Wc = W;
+        Wc.on = 0;                               // the cone's mirror reads are older than the block
+        Lane Lc;
+        load_base(g, b, C, Lc, ra);
+        const int64_t rc_end = (ra + P.T - 2 < rb) ? ra + P.T - 2 : rb;
+        for (int64_t r = ra; r <= rc_end; ++r) {
+            const int tau = (int)(r - ra);
+            const int64_t act = C.lo + (int64_t)H1 * tau;
+            do_row<false>(g, b, Wc, pw, C, Lc, wave_tot, tblE, tblF, qa, rinfo[tau], r, rc_end, act, tau & 1,
+                          0, 0, 0);
+            const int64_t j0 = C.lo + (int64_t)threadIdx.x * K;
+            #pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const int64_t j = j0 + i;
+                if (j >= W.lo && j <= D && j >= act) win[tau][j - W.lo] = Lc.up[i];
+            }
+        }
+        __syncthreads();
+    }
+
+    Lane L;
+    load_base(g, b, R, L, ra);
+    for (int64_t r = ra; r <= rb; ++r) {
+        const int tau = (int)(r - ra);
+        const int par = tau & 1;
+        const int64_t act = R.exact ? R.lo : R.own_lo - (int64_t)H1 * (P.T - tau) + 1;
+        const RowInfo ri = rinfo[tau];
+        double pe = far ? do_row<true>(g, b, W, pw, R, L, wave_tot, tblE, tblF, qa, ri, r, rb, act, par, 1, 0, 0)
+                        : do_row<false>(g, b, W, pw, R, L, wave_tot, tblE, tblF, qa, ri, r, rb, act, par, 1,
+                                        write_win, is_strip);
+        pe = wave_sum63(pe);
+        if ((threadIdx.x & 63) == 63) pe_lds[tau][threadIdx.x >> 6] = pe;
+        if (write_win) __syncthreads();          // the window row written above is read by the next row
+    }
+    __syncthreads();
+    if (threadIdx.x < nrows) {
+        const int tau = threadIdx.x;
+        const int64_t r = ra + tau;
+        double tot = 0.0;
+        for (int w2 = 0; w2 < NW; ++w2) tot += pe_lds[tau][w2];
+        if (is_strip && w == 0) {
+            const cd v0 = b.Phi[r] * b.Et[r];
+            tot += 0.5 * norm2(v0);
+        }
+        b.Ppart[r * P.nwg + w] = tot;
+    }
+}
+
+}  // namespace
+
+int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1)
+{
+    hipLaunchKernelGGL(k_block, dim3(c->plan.nb), dim3(BM_THREADS), 0, c->stream, c->g, c->b, c->plan, m0, m1, s0, s1);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+// Planner: rows per block T, halo, and the split of the columns into
+// workgroups of about equal cost (columns with mirror reads -- the strip and
+// the near part of the outgoing region -- count MIRROR_COST times a far
+// column), about one workgroup per compute unit.
+static const double MIRROR_COST = 2.0;
+static const int NCU = 256;
+
+int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n)
+{
+    const int64_t D = p->D, Nx = p->Nx;
+    const int targets[] = {32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
+    for (int T : targets) {
+        if (T > BM_TMAX || T > D) continue;
+        Plan P;
+        memset(&P, 0, sizeof P);
+        P.T = T;
+        P.H = H;
+        P.hmax = (H + 1) * T - 1;
+        const int64_t room = BM_CAP - P.hmax;           // owned columns a halo workgroup can hold
+        if (room < 64) continue;
+        // the near part ends where far workgroups' halos hold no mirror reads
+        P.near_end = 2 * D + P.hmax;
+        if (P.near_end > Nx) P.near_end = Nx;
+        const int64_t near_cols = P.near_end - D;
+        const int64_t far_cols = Nx - P.near_end;
+        // widths: at least twice the halo, at most what a workgroup holds
+        int64_t minw = 2 * (int64_t)P.hmax;
+        if (minw < 64) minw = 64;
+        if (minw > room) minw = room;
+        double budget = (MIRROR_COST * (double)(D + near_cols) + (double)far_cols) / NCU;
+        int ok = 0;
+        for (int it = 0; it < 200; ++it, budget *= 1.02) {
+            int64_t wm = (int64_t)(budget / MIRROR_COST), wf = (int64_t)budget;
+            if (wm < minw) wm = minw;
+            if (wf < minw) wf = minw;
+            if (wm > room) wm = room;
+            if (wf > room) wf = room;
+            // strip
+            P.cone_L0 = T + (int64_t)H * (T - 1);
+            const int can_cone = (D + 1 - P.cone_L0 >= T) && (P.cone_L0 <= BM_CAP);
+            if (D <= BM_CAP && (D <= wm + wm / 2 || !can_cone)) {
+                P.cone_mode = 0;
+                P.Gs = 1;
+                P.strip_w = D;
+            } else if (can_cone) {
+                P.cone_mode = 1;
+                int64_t Gs = (D + wm - 1) / wm;
+                if (Gs < 2) Gs = 2;
+                P.strip_w = (D + Gs - 1) / Gs;
+                P.Gs = (int)((D + P.strip_w - 1) / P.strip_w);
+                if (P.strip_w + 1 - P.hmax < T) break;            // halo mirror reads must be older than the block
+                if (D - (int64_t)(P.Gs - 1) * P.strip_w + P.hmax > BM_CAP) break;
+            } else {
+                break;
+            }
+            // near part (the first near workgroup needs no halo)
+            int64_t Gn = (near_cols + wm - 1) / wm;
+            if (Gn < 1) Gn = 1;
+            P.near_w = (near_cols + Gn - 1) / Gn;
+            P.Gn = (int)((near_cols + P.near_w - 1) / P.near_w);
+            // far part
+            int64_t Gf = (far_cols > 0) ? (far_cols + wf - 1) / wf : 0;
+            P.far_w = Gf ? (far_cols + Gf - 1) / Gf : 1;
+            Gf = Gf ? (far_cols + P.far_w - 1) / P.far_w : 0;
+            P.Gm = P.Gn + (int)Gf;
+            P.nwg = P.Gs + P.Gm;
+            if (P.near_w > room && P.Gn > 1) continue;
+            if (P.far_w > room) continue;
+            if (P.nwg <= NCU || (wm >= room && wf >= room)) { ok = 1; break; }
+        }
+        if (!ok) continue;
+        // halos start right of column 0
+        if (P.Gn > 1 && D + 1 + P.near_w - P.hmax < 1) continue;
+        P.win_lo = D - T + 1 < 1 ? 1 : D - T + 1;
+        P.nb = ((P.nwg + 7) / 8) * 8;
+        *out = P;
+        return FDTD_OK;
+    }
+    snprintf(why, n, "no block decomposition fits (D=%lld, Nx=%lld, halo %d per row)", (long long)D,
+             (long long)Nx, H + 1);
+    return FDTD_EINVAL;
+}

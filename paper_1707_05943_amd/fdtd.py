@@ -24,7 +24,7 @@ STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", 
 # every symbol include/fdtd.h declares
 EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_boundary_tables",
            "fdtd_march", "fdtd_current_row", "fdtd_readout", "fdtd_sync", "fdtd_destroy",
-           "fdtd_strerror", "fdtd_last_error")
+           "fdtd_describe", "fdtd_strerror", "fdtd_last_error")
 
 
 class FdtdParams(ctypes.Structure):
@@ -64,6 +64,7 @@ def load(path: str = LIB_PATH):
     lib.fdtd_readout.argtypes = [vp, i32, i64, vp, i64, i32]
     lib.fdtd_sync.argtypes = [vp]
     lib.fdtd_destroy.argtypes = [vp]
+    lib.fdtd_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
     lib.fdtd_strerror.argtypes = [ctypes.c_int]
     lib.fdtd_strerror.restype = ctypes.c_char_p
     lib.fdtd_last_error.argtypes = [vp]
@@ -90,6 +91,18 @@ def workspace_size(inst) -> int:
     if rc:
         raise FdtdError(rc, lib.fdtd_last_error(None).decode())
     return int(n.value)
+
+
+def describe(inst) -> dict:
+    """The work decomposition the library uses for this instance."""
+    import json
+    lib = load()
+    p = params(inst)
+    buf = ctypes.create_string_buffer(1024)
+    rc = lib.fdtd_describe(ctypes.byref(p), buf, 1024)
+    if rc:
+        raise FdtdError(rc, lib.fdtd_last_error(None).decode())
+    return json.loads(buf.value.decode())
 
 
 class Solver:

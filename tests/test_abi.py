@@ -49,14 +49,23 @@ def test_workspace_size_rejects_invalid_parameters(kw):
 
 
 def test_workspace_size_counts_the_ring():
-    inst = W.small_gauss()
-    n = fdtd.workspace_size(inst)
-    ring = (inst.D + 2) * (inst.Nx + 1) * 16
-    assert ring <= n < ring + 64 * (inst.Nt + 1) * 16 + (1 << 20)
-    big = W.large_gauss()
-    nb = fdtd.workspace_size(big)
-    assert nb >= (big.D + 2) * (big.Nx + 1) * 16            # ~42 GB ring
-    assert nb < 50 * 2**30
+    for inst in (W.small_gauss(), W.large_gauss()):
+        n = fdtd.workspace_size(inst)
+        plan = fdtd.describe(inst)
+        rows = plan["ring_rows"]
+        assert rows == inst.D + 2 * plan["T"] + 2
+        ring = rows * (inst.Nx + 1) * 16 + rows * (inst.D + 1) * 16     # ring and its diagonal strip copy
+        tables = (inst.Nt + 1) * (16 * 4 + 8 * (2 + plan["nwg"])) + (inst.Nx + 1) * 16
+        assert ring <= n <= ring + tables + 16 * 256
+    assert fdtd.workspace_size(W.large_gauss()) < 50 * 2**30     # ~42 GB ring + 1.6 GB strip copy
+
+
+def test_decomposition_of_the_large_workload():
+    plan = fdtd.describe(W.large_gauss())
+    # about one workgroup per compute unit, strip in several workgroups with a cone
+    assert plan["cone_mode"] == 1 and plan["nwg"] <= 256 and plan["T"] == 32
+    small = fdtd.describe(W.small_gauss())
+    assert small["cone_mode"] == 0 and small["Gs"] == 1
 
 
 def test_strerror_texts():

@@ -50,6 +50,9 @@ MARCH_CASES = {
     "gauss_D2_min": _gauss(2, 3, 50, 0.1, 0.4, 12),                 # Nx = D+1
     "gauss_D40_Nx1025": _gauss(40, 1025, 200, 0.025, 0.6, 13),      # one column in the second block
     "gauss_D1200_Nx3100": _gauss(1200, 3100, 2600, 0.0025, 0.5, 14),  # strip wider than a block
+    # coarse grid, |alpha| = 0.47: the within-row recurrence carries across many columns
+    "coarse_alpha": W.Instance(name="coarse_alpha", Nx=1500, D=24, Nt=300, Delta=0.5, omega0=4.5, Gamma=1.0,
+                               incident=W.INC_GAUSS2, k=4.5, x0=-6.0 - 8 * 3.0, width=3.0, phase=0.3),
     "exp2": _fam("exp2", W.INC_EXP2),
     "exp1": _fam("exp1", W.INC_EXP1, alpha=0.5, Gamma=1.5),
     "plane": _fam("plane", W.INC_PLANE, k=1.7, Nt=300),
@@ -72,6 +75,12 @@ def march_and_compare(inst, sol, E, rows, n_tau, label):
     """March the library to each of `rows` in turn and compare the row and the
     chi readout there with the oracle; then the final ring (D+2 rows) and
     P_e(t_r) over every row."""
+    # always compare around the peak of P_e too, so that the 1% floor is
+    # taken from rows where the field is alive
+    pre = oracle.march(inst, E, want_ring=False)["pe"]
+    if np.all(np.isfinite(pre)):
+        rp = int(np.argmax(pre))
+        rows = list(rows) + [max(1, rp // 2), max(1, rp), min(inst.Nt, (3 * rp) // 2)]
     rows = sorted(set(int(r) for r in rows) | {inst.Nt})
     ref = oracle.march(inst, E, chi_rows=rows, n_tau=n_tau, snap_rows=rows)
     scale = max(np.linalg.norm(v) for v in ref["snaps"])
