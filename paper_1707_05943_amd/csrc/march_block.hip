@@ -35,7 +35,10 @@
 //    bound at every row;
 //  * mirror reads of the strip at lags below T (only columns j < T do this)
 //    come from a window in LDS that the strip's first workgroup fills from a
-//    cone of columns at the strip's right end, computed the same way.
+//    cone of columns at the strip's right end, computed the same way by its
+//    second half of threads in the same row pass;
+//  * all other mirror reads come from a copy of the strip stored along
+//    anti-diagonals, so that the reads of one row are contiguous.
 // The kernel boundary between launches makes every write of a launch
 // visible to the next one; no flags or fences are needed.
 
@@ -48,29 +51,23 @@ namespace {
 constexpr int NT = BM_THREADS;
 constexpr int K = BM_K;
 constexpr int NW = NT / 64;
-constexpr int TBL = BM_CAP + BM_TMAX;      // LDS table entries: indexes r - j over one block
+constexpr int TBL = 1600;                  // LDS table entries (>= BM_CAP + BM_TMAX, and 2 x (NT/2 K + BM_TMAX))
 
 __device__ inline cd zero() { return mk(0.0, 0.0); }
 __device__ inline int64_t dec_slot(int64_t s, int64_t R) { return s == 0 ? R - 1 : s - 1; }
 __device__ inline int64_t inc_slot(int64_t s, int64_t R) { return s + 1 == R ? 0 : s + 1; }
-__device__ inline int64_t slot_of(int64_t q, int64_t R) { return q % R; }
+__device__ inline int64_t slot_or_neg(int64_t rho, int64_t R) { return rho < 0 ? -1 : rho % R; }
 
 __device__ inline cd phi_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Phi[q] : zero(); }
 __device__ inline cd et_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Et[q] : zero(); }
 
-// psi at column i of row rho, given rho's ring slot: zero before t = 0, the
-// exact solution at columns <= 0, the ring otherwise
-__device__ inline cd rd_slot(const Geom& g, const Bufs& b, int64_t i, int64_t rho, int64_t slot)
-{
-    if (rho < 0) return zero();
-    if (i <= 0) return b.Phi[rho - i] * b.Et[rho];
-    return b.ring[slot * g.C + i];
-}
-
+// psi at column i, row rho from memory: zero before t = 0, the exact solution
+// at columns <= 0, the ring otherwise
 __device__ inline cd rd(const Geom& g, const Bufs& b, int64_t i, int64_t rho)
 {
     if (rho < 0) return zero();
-    return rd_slot(g, b, i, rho, slot_of(rho, g.R));
+    if (i <= 0) return b.Phi[rho - i] * b.Et[rho];
+    return b.ring[(rho % g.R) * g.C + i];
 }
 
 // cross-lane moves with DPP (GFX9 encodings); lanes without a source get 0
@@ -89,14 +86,15 @@ __device__ __forceinline__ cd dpp_cd(cd v) { return mk(dpp_f64<CTRL, RM>(v.re), 
 constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
 constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143, DPP_WAVE_SHR1 = 0x138;
 
-// Powers of alpha for the scan of psi = alpha psi_left + beta over a wave:
-// a[i] = alpha^i (i <= K), s[k] = alpha^(K 2^k) (k < 4), and per lane l
-// m15 = alpha^(K((l mod 32) - 15)), m31 = alpha^(K(l - 31)), lp = alpha^(K l),
-// m64 = alpha^(64 K).
+// Powers of alpha for the scan of psi = alpha psi_left + beta (kept in LDS):
+// a[i] = alpha^i (i <= K), s[k] = alpha^(K 2^k) (k < 4), m64 = alpha^(64 K),
+// and per lane l: m15 = alpha^(K((l mod 32) - 15)), m31 = alpha^(K(l - 31)),
+// lp = alpha^(K l).
 struct Pow {
     cd a[K + 1];
     cd s[4];
-    cd m15, m31, lp, m64;
+    cd m64;
+    cd m15[64], m31[64], lp[64];
 };
 
 __device__ inline cd cpow_u(cd x, int e)
@@ -110,31 +108,33 @@ __device__ inline cd cpow_u(cd x, int e)
     return r;
 }
 
-__device__ inline Pow make_pow(cd al)
+__device__ void fill_pow(cd al, Pow& p)
 {
-    Pow p;
-    p.a[0] = mk(1.0, 0.0);
-    for (int i = 1; i <= K; ++i) p.a[i] = p.a[i - 1] * al;
-    cd m = p.a[K];
-    for (int k = 0; k < 4; ++k) { p.s[k] = m; m = m * m; }
-    const int lane = threadIdx.x & 63;
-    const int l32 = lane & 31;
-    p.m15 = (l32 >= 16) ? cpow_u(p.a[K], l32 - 15) : mk(0.0, 0.0);
-    p.m31 = (lane >= 32) ? cpow_u(p.a[K], lane - 31) : mk(0.0, 0.0);
-    p.lp = cpow_u(p.a[K], lane);
-    p.m64 = cpow_u(p.a[K], 64);
-    return p;
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const cd aK = cpow_u(al, K);
+        const int l32 = t & 31;
+        p.m15[t] = (l32 >= 16) ? cpow_u(aK, l32 - 15) : mk(0.0, 0.0);
+        p.m31[t] = (t >= 32) ? cpow_u(aK, t - 31) : mk(0.0, 0.0);
+        p.lp[t] = cpow_u(aK, t);
+    } else if (t == 64) {
+        p.a[0] = mk(1.0, 0.0);
+        for (int i = 1; i <= K; ++i) p.a[i] = p.a[i - 1] * al;
+        cd m = p.a[K];
+        for (int k = 0; k < 4; ++k) { p.s[k] = m; m = m * m; }
+        p.m64 = cpow_u(p.a[K], 64);
+    }
 }
 
 // inclusive scan over a wave of x_l = v_l + alpha^K x_{l-1}
-__device__ __forceinline__ cd wave_scan(cd x, const Pow& P)
+__device__ __forceinline__ cd wave_scan(cd x, const Pow& P, int lane)
 {
     x += P.s[0] * dpp_cd<DPP_ROW_SHR1, 0xF>(x);
     x += P.s[1] * dpp_cd<DPP_ROW_SHR2, 0xF>(x);
     x += P.s[2] * dpp_cd<DPP_ROW_SHR4, 0xF>(x);
     x += P.s[3] * dpp_cd<DPP_ROW_SHR8, 0xF>(x);
-    x += P.m15 * dpp_cd<DPP_ROW_BCAST15, 0xA>(x);
-    x += P.m31 * dpp_cd<DPP_ROW_BCAST31, 0xC>(x);
+    x += P.m15[lane] * dpp_cd<DPP_ROW_BCAST15, 0xA>(x);
+    x += P.m31[lane] * dpp_cd<DPP_ROW_BCAST31, 0xC>(x);
     return x;
 }
 
@@ -150,18 +150,10 @@ __device__ __forceinline__ double wave_sum63(double v)
     return v;
 }
 
-struct Range {
-    int64_t lo;      // column of thread 0's first value
-    int64_t hi;      // one past the last column
-    int64_t own_lo;  // first column written to the ring (own_lo >= hi: none)
-    int exact;       // the value left of `lo` is exact (from memory) in every row
-};
-
 struct Win {                     // the strip's right end for the rows of the current strip block
     cd (*w)[BM_TMAX];
     int64_t lo;                  // first column held
     int64_t row0;                // first row held (the block's first row)
-    int on;                      // mirror reads of rows >= row0 go to the window
 };
 
 // Per-row values shared by the whole workgroup (computed once per block)
@@ -175,12 +167,27 @@ struct RowInfo {
     int delay_on;                // r - 1 >= D
 };
 
-// Per-thread state of one column range through a block.
+// A thread's column range and role.  Threads t0 .. t0+nt-1 of the workgroup
+// march columns lo .. hi-1 (thread t0+i from lo + iK); the range's first
+// thread takes the value left of lo as the carry (exact, or zero for a halo).
+struct Seg {
+    int64_t lo, hi, own_lo;      // own_lo: first column written to the ring
+    int t0, w0;                  // first thread and first wave of the segment
+    int exact;                   // the value left of lo is exact in every row
+    int trap;                    // trapezoid: the first evaluated column moves H+1 right per row
+    int write_ring, write_md, write_win, use_win;
+    int64_t qa;                  // q = r - j of table entry 0
+    const cd* tE;                // far: Et[q] - Et[q+D]; otherwise Et[q]
+    const cd* tP;                // Phi[q]
+    const cd* tE2;               // Et[q+D] (near columns)
+};
+
+// Per-thread state through a block.
 struct Lane {
-    cd up[K];                    // psi(j, r-1) for the thread's columns
-    cd upL;                      // psi(j0-1, r-1)
+    cd up[K + 1];                // psi(j0-1+i, r-1): the left neighbour, then the thread's columns
     cd dA[K + 1];                // row r-1-D at columns j0-1-D .. j0+K-1-D
     cd dB[K + 1];                // row r-D at the same columns
+    cd mA[K], mB[K];             // mirror values of this row: diagonals r-D and r-D-1
     int64_t sd;                  // row of Md holding diagonal r - j0 (the thread's first column)
 };
 
@@ -201,30 +208,50 @@ __device__ __forceinline__ void load_delay_row(const Geom& g, const Bufs& b, int
     }
 }
 
-// One row of one column range.
-//  FAR: every column of the range lies beyond 2D, where all source terms are
-//       exact; the tables dE[q] = Et[q] - Et[q+D] and F[q] = Phi[q] (q = r - j)
-//       come from LDS.
-//  otherwise: the generic update; mirror reads come from the diagonal copy
-//       Md (contiguous along the row) or, for the strip's first workgroup and
-//       rows of the current block, from the LDS window.
+// mirror values needed by columns j0.. at the row whose diagonals r-D and
+// r-D-1 sit in Md rows sA and sB: psi(D-j, r-j), psi(D-j+1, r-j) for strip
+// columns, psi(2D-j, r-j+D), psi(2D-j+1, r-j+D) for near columns (column 0
+// entries are left to the exact solution)
+__device__ __forceinline__ void load_mirror(const Geom& g, const Bufs& b, int64_t j0, int64_t sA, int64_t sB,
+                                            cd* mA, cd* mB)
+{
+    const int64_t D = g.D;
+    const cd* rowA = b.Md + sA * g.Mc;
+    const cd* rowB = b.Md + sB * g.Mc;
+    #pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t j = j0 + i;
+        int64_t c = -1;
+        if (j >= 1 && j <= D) c = D - j;
+        else if (j > D && j <= 2 * D) c = 2 * D - j;
+        mA[i] = (c >= 1) ? rowA[c] : zero();
+        mB[i] = (c >= 0) ? rowB[c + 1] : zero();
+    }
+}
+
+// One row of one thread's segment.  FAR: every column of the range lies
+// beyond 2D, where all source terms are exact (tables dE and Phi).
 // Returns this thread's share of sum |psi|^2 over the owned columns.
 template <bool FAR>
-__device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win& W, const Pow& P, const Range& R,
-                                         Lane& L, cd (*wave_tot)[NW], const cd* tblE, const cd* tblF, int64_t qa,
-                                         const RowInfo& ri, int64_t r, int64_t rb, int64_t act_lo, int par,
-                                         int write_ring, int write_win, int write_md)
+__device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win& W, const Pow& P, const Seg& S,
+                                         Lane& L, cd (*wave_tot)[NW], const RowInfo& ri, const RowInfo* rnext,
+                                         int64_t r, int64_t rb, int64_t act_lo, int par)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t j0 = R.lo + (int64_t)tid * K;
+    const int64_t j0 = S.lo + (int64_t)(tid - S.t0) * K;
     const int64_t D = g.D;
-    const int64_t jmax = (R.hi - 1 < g.Nx) ? R.hi - 1 : g.Nx;
+    const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
     const int any = (j0 + K - 1 >= act_lo) && (j0 <= jmax);
     const double g8 = 0.125 * g.Gamma, g2 = 0.5 * g.Gamma;
 
-    // prefetch the delay row of the next row
+    // prefetch the delay row (and the mirror values) of the next row
     cd nx[K + 1];
-    if (any && r + 1 <= rb) load_delay_row(g, b, j0, r + 1 - D, ri.slot_pf, nx);
+    cd nA[K], nB[K];
+    const int pf = any && r + 1 <= rb;
+    if (pf) {
+        load_delay_row(g, b, j0, r + 1 - D, ri.slot_pf, nx);
+        if (!FAR) load_mirror(g, b, j0, rnext->slot, rnext->slot_m1, nA, nB);
+    }
 
     cd u[K];
     if (any) {
@@ -233,60 +260,58 @@ __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win
             #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int64_t j = j0 + i;
-                const cd left = (i == 0) ? L.upL : L.up[i - 1];
-                cd S = zero();
-                if (ri.delay_on) S = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
-                const int64_t t = r - j - qa;
-                S += kr * tblE[t] + ri.drv * tblF[t];
-                cd v = g.cA * left + g.cB * L.up[i] + g.cinv * S;
+                cd Sv = zero();
+                if (ri.delay_on) Sv = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
+                const int64_t t = r - j - S.qa;
+                Sv += kr * S.tE[t] + ri.drv * S.tP[t];
+                const cd v = g.cA * L.up[i] + g.cB * L.up[i + 1] + g.cinv * Sv;
                 u[i] = (j >= act_lo && j <= jmax) ? v : zero();
             }
         } else {
-            const cd* mdA = b.Md + ri.slot * g.Mc;       // diagonal r - D
-            const cd* mdB = b.Md + ri.slot_m1 * g.Mc;    // diagonal r - D - 1
             #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int64_t j = j0 + i;
-                const cd left = (i == 0) ? L.upL : L.up[i - 1];
-                if (!(j >= act_lo && j <= jmax)) { u[i] = zero(); continue; }
-                cd S = zero();
-                if (ri.delay_on) S = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
+                cd Sv = zero();
+                if (ri.delay_on) Sv = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
                 cd src = zero();
                 const int64_t q = r - j;
-                if (q >= 0) {
-                    const cd et = b.Et[q];
+                const int64_t t = q - S.qa;
+                const int ok = (j >= act_lo && j <= jmax);
+                if (ok && q >= 0) {
+                    const cd et = S.tE[t];
+                    const cd ph = S.tP[t];
                     cd mir;
                     if (j <= D) {
                         // bar(D-j, r-j): psi(D-j, q) on diagonal r-D, psi(D-j+1, q) on r-D-1
-                        const int inwin = W.on && q >= W.row0;
-                        cd m0, m1;
-                        if (j == D) m0 = b.Phi[q] * b.Et[q];
-                        else m0 = inwin ? W.w[q - W.row0][D - j - W.lo] : mdA[D - j];
-                        m1 = inwin ? W.w[q - W.row0][D - j + 1 - W.lo] : mdB[D - j + 1];
+                        const int inwin = S.use_win && q >= W.row0;
+                        const int64_t wr = inwin ? q - W.row0 : 0;
+                        const int64_t wc = inwin ? D - j - W.lo : 0;
+                        const cd w0 = inwin && j < D ? W.w[wr][wc] : zero();
+                        const cd w1 = inwin ? W.w[wr][wc + 1] : zero();
+                        const cd m0 = (j == D) ? ph * et : (inwin ? w0 : L.mA[i]);
+                        const cd m1 = inwin ? w1 : L.mB[i];
                         mir = 0.5 * (m0 + m1);
                     } else {
                         mir = et * ri.half_qr;
                     }
                     src = et * ri.half_pr - mir;
-                    S += ri.drv * b.Phi[q];
+                    Sv += ri.drv * ph;
                 }
-                if (j > D) {
-                    const int64_t q2 = q + D;
-                    if (q2 >= 0) {
-                        const cd et2 = b.Et[q2];
-                        cd mir2;
-                        if (j <= 2 * D) {
-                            // bar(2D-j, r-j+D): diagonals r-D and r-D-1 again
-                            const cd m0 = (j == 2 * D) ? b.Phi[q2] * b.Et[q2] : mdA[2 * D - j];
-                            mir2 = 0.5 * (m0 + mdB[2 * D - j + 1]);
-                        } else {
-                            mir2 = et2 * ri.half_qr;
-                        }
-                        src += mir2 - et2 * ri.half_pr;
+                if (ok && j > D && q + D >= 0) {
+                    const cd et2 = S.tE2[t];
+                    cd mir2;
+                    if (j <= 2 * D) {
+                        // bar(2D-j, r-j+D): diagonals r-D and r-D-1 again
+                        const cd m0 = (j == 2 * D) ? b.Phi[q + D] * et2 : L.mA[i];
+                        mir2 = 0.5 * (m0 + L.mB[i]);
+                    } else {
+                        mir2 = et2 * ri.half_qr;
                     }
+                    src += mir2 - et2 * ri.half_pr;
                 }
-                S -= g2 * src;
-                u[i] = g.cA * left + g.cB * L.up[i] + g.cinv * S;
+                Sv -= g2 * src;
+                const cd v = g.cA * L.up[i] + g.cB * L.up[i + 1] + g.cinv * Sv;
+                u[i] = ok ? v : zero();
             }
         }
         #pragma unroll
@@ -296,25 +321,25 @@ __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win
         for (int i = 0; i < K; ++i) u[i] = zero();
     }
 
-    // carry into the range
+    // carry into the segment
     cd carry0 = zero();
-    if (R.exact && tid == 0) {
-        const int64_t c = R.lo - 1;
+    if (S.exact && tid == S.t0) {
+        const int64_t c = S.lo - 1;
         carry0 = (c <= 0) ? b.Phi[r - c] * b.Et[r] : b.ring[ri.slot * g.C + c];
     }
 
-    // x_t = u_last + alpha^K x_{t-1}: inclusive scan over the threads
+    // x_t = u_last + alpha^K x_{t-1}: inclusive scan over the segment's threads
     cd x = u[K - 1];
-    if (tid == 0) x += P.a[K] * carry0;
-    x = wave_scan(x, P);
+    if (tid == S.t0) x += P.a[K] * carry0;
+    x = wave_scan(x, P, lane);
     if (lane == 63) wave_tot[par][wv] = x;
     const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
     __syncthreads();
     cd wcarry = zero();
-    for (int w2 = 0; w2 < wv; ++w2) wcarry = P.m64 * wcarry + wave_tot[par][w2];
+    for (int w2 = S.w0; w2 < wv; ++w2) wcarry = P.m64 * wcarry + wave_tot[par][w2];
     // the value just left of this thread's first column
-    cd cin = prevx + P.lp * wcarry;
-    if (tid == 0) cin = carry0;
+    cd cin = prevx + P.lp[lane] * wcarry;
+    if (tid == S.t0) cin = carry0;
 
     double pe = 0.0;
     if (any) {
@@ -326,44 +351,87 @@ __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win
             const int act = (j >= act_lo && j <= jmax);
             const cd v = act ? u[i] + P.a[i + 1] * cin : zero();
             u[i] = v;
-            if (act && j >= R.own_lo) {
-                if (write_ring) row[j] = v;
-                if (write_md) b.Md[sd * g.Mc + j] = v;
+            if (act && j >= S.own_lo) {
+                if (S.write_ring) row[j] = v;
+                if (S.write_md) b.Md[sd * g.Mc + j] = v;
                 const double m2 = norm2(v);
                 pe += (j == g.Nx) ? 0.5 * m2 : m2;
             }
-            if (write_win && act && j >= W.lo && j <= D) W.w[r - W.row0][j - W.lo] = v;
+            if (S.write_win && act && j >= W.lo && j <= D) W.w[r - W.row0][j - W.lo] = v;
             sd = dec_slot(sd, g.R);
         }
         // advance: psi(j0-1, r) is the carry that entered this thread
-        L.upL = cin;
+        L.up[0] = cin;
         #pragma unroll
-        for (int i = 0; i < K; ++i) L.up[i] = u[i];
+        for (int i = 0; i < K; ++i) L.up[i + 1] = u[i];
         #pragma unroll
         for (int i = 0; i <= K; ++i) { L.dA[i] = L.dB[i]; L.dB[i] = nx[i]; }
+        if (!FAR && pf) {
+            #pragma unroll
+            for (int i = 0; i < K; ++i) { L.mA[i] = nA[i]; L.mB[i] = nB[i]; }
+        }
         L.sd = inc_slot(L.sd, g.R);
     }
     return pe;
 }
 
-__device__ inline int64_t slot_or_neg(int64_t rho, int64_t R) { return rho < 0 ? -1 : rho % R; }
-
-// the block's base row (row r0-1) and the delay rows of its first row
-__device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Range& R, Lane& L, int64_t r0)
+// the block's base row (row r0-1), the delay rows and mirror values of its first row
+__device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Seg& S, Lane& L, int64_t r0,
+                                          const RowInfo& ri0)
 {
-    const int tid = threadIdx.x;
-    const int64_t j0 = R.lo + (int64_t)tid * K;
+    const int64_t j0 = S.lo + (int64_t)(threadIdx.x - S.t0) * K;
     #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int64_t j = j0 + i;
-        L.up[i] = (j <= g.Nx && j < R.hi) ? rd(g, b, j, r0 - 1) : zero();
+        L.up[i + 1] = (j <= g.Nx && j < S.hi) ? rd(g, b, j, r0 - 1) : zero();
     }
-    L.upL = (j0 - 1 <= g.Nx) ? rd(g, b, j0 - 1, r0 - 1) : zero();
+    L.up[0] = (j0 - 1 <= g.Nx) ? rd(g, b, j0 - 1, r0 - 1) : zero();
     const int64_t rA = r0 - 1 - g.D, rB = r0 - g.D;
     load_delay_row(g, b, j0, rA, slot_or_neg(rA, g.R), L.dA);
     load_delay_row(g, b, j0, rB, slot_or_neg(rB, g.R), L.dB);
+    load_mirror(g, b, j0, ri0.slot, ri0.slot_m1, L.mA, L.mB);
     const int64_t d = r0 - j0 + g.D;                    // diagonal r0 - j0, offset by D
     L.sd = ((d % g.R) + g.R) % g.R;
+}
+
+// tables of q = r - j over a block for the columns lo..hi-1 and rows ra..rb
+__device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64_t n, cd* tE, cd* tP, cd* tE2,
+                            int t_begin, int t_count)
+{
+    for (int64_t t = threadIdx.x - t_begin; t <= n; t += t_count) {
+        if (t < 0) continue;
+        const int64_t q = qa + t;
+        if (far) {
+            tE[t] = et_at(b, q) - et_at(b, q + D);
+            tP[t] = phi_at(b, q);
+        } else {
+            tE[t] = et_at(b, q);
+            tP[t] = phi_at(b, q);
+            if (tE2) tE2[t] = et_at(b, q + D);
+        }
+    }
+}
+
+// the rows of a block for one thread's segment
+template <bool FAR>
+__device__ __forceinline__ void march_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw, const Seg& S,
+                                           cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
+                                           int64_t ra, int64_t rb, int H1, int T, int cone, int use_win)
+{
+    Lane L;
+    load_base(g, b, S, L, ra, rinfo[0]);
+    for (int64_t r = ra; r <= rb; ++r) {
+        const int tau = (int)(r - ra);
+        const int par = tau & 1;
+        int64_t act = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
+        if (cone && threadIdx.x >= NT / 2 && tau > T - 2) act = S.hi;     // the cone stops a row early
+        const RowInfo ri = rinfo[tau];
+        const RowInfo* rn = &rinfo[tau + 1 < BM_TMAX ? tau + 1 : tau];
+        double pe = do_row<FAR>(g, b, W, pw, S, L, wave_tot, ri, rn, r, rb, act, par);
+        pe = wave_sum63(pe);
+        if ((threadIdx.x & 63) == 63) pe_lds[tau][threadIdx.x >> 6] = pe;
+        if (use_win) __syncthreads();            // window rows written above are read by the next row
+    }
 }
 
 __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
@@ -372,9 +440,9 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
     __shared__ cd wave_tot[2][NW];
     __shared__ double pe_lds[BM_TMAX][NW];
     __shared__ cd win[BM_TMAX][BM_TMAX];
-    __shared__ cd tblE[TBL];
-    __shared__ cd tblF[TBL];
+    __shared__ cd tab[3][TBL];
     __shared__ RowInfo rinfo[BM_TMAX];
+    __shared__ Pow pw;
 
     const int bid = blockIdx.x;
     const int w = (bid % 8) * (P.nb / 8) + bid / 8;     // neighbouring column ranges share an XCD
@@ -385,17 +453,14 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
     if (rb < ra) return;
 
     const int64_t D = g.D;
-    Range R;
+    int64_t c0, c1;
+    int exact;
     if (is_strip) {
-        const int64_t c0 = 1 + (int64_t)w * P.strip_w;
-        const int64_t c1 = (w == P.Gs - 1) ? D + 1 : c0 + P.strip_w;
-        R.exact = (w == 0);
-        R.lo = R.exact ? c0 : c0 - P.hmax;
-        R.hi = c1;
-        R.own_lo = c0;
+        c0 = 1 + (int64_t)w * P.strip_w;
+        c1 = (w == P.Gs - 1) ? D + 1 : c0 + P.strip_w;
+        exact = (w == 0);
     } else {
         const int m = w - P.Gs;
-        int64_t c0, c1;
         if (m < P.Gn) {
             c0 = D + 1 + (int64_t)m * P.near_w;
             c1 = (m == P.Gn - 1) ? P.near_end + 1 : c0 + P.near_w;
@@ -404,17 +469,51 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
             c0 = P.near_end + 1 + (int64_t)f * P.far_w;
             c1 = (m == P.Gm - 1) ? g.Nx + 1 : c0 + P.far_w;
         }
-        R.exact = (m == 0);
-        R.lo = R.exact ? c0 : c0 - P.hmax;
-        R.hi = c1;
-        R.own_lo = c0;
+        exact = (m == 0);
     }
     const int H1 = P.H + 1;
-    const Pow pw = make_pow(g.alpha);
-    const int far = (!is_strip) && (R.lo > 2 * D);
+    const int64_t lo = exact ? c0 : c0 - P.hmax;
+    const int far = (!is_strip) && (lo > 2 * D);
     const int nrows = (int)(rb - ra + 1);
+    const int cone = is_strip && w == 0 && P.cone_mode == 1;
+    const int use_win = is_strip && w == 0;
 
-    // per-row values of this block
+    // this thread's segment: the whole workgroup, or (strip workgroup 0 in
+    // cone mode) the first half for its columns and the second half for the cone
+    Seg S;
+    S.t0 = 0;
+    S.w0 = 0;
+    S.lo = lo;
+    S.hi = c1;
+    S.own_lo = c0;
+    S.exact = exact;
+    S.trap = !exact;
+    S.write_ring = 1;
+    S.write_md = is_strip;
+    S.write_win = use_win && (P.cone_mode == 0);
+    S.use_win = use_win;
+    S.qa = ra - (c1 - 1);
+    S.tE = tab[0];
+    S.tP = tab[1];
+    S.tE2 = tab[2];
+    if (cone && threadIdx.x >= NT / 2) {
+        S.t0 = NT / 2;
+        S.w0 = NW / 2;
+        S.lo = D + 1 - P.cone_L0;
+        S.hi = D + 1;
+        S.own_lo = D + 1;                        // nothing owned: the cone only fills the window
+        S.exact = 0;
+        S.trap = 1;
+        S.write_ring = 0;
+        S.write_md = 0;
+        S.write_win = 1;
+        S.use_win = 0;                           // the cone's mirror reads are older than the block
+        S.qa = ra - D;
+        S.tE = tab[0] + TBL / 2;
+        S.tP = tab[1] + TBL / 2;
+    }
+
+    // per-row values of this block, scan constants, tables
     if (threadIdx.x < nrows) {
         const int64_t r = ra + threadIdx.x;
         RowInfo ri;
@@ -427,15 +526,14 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
         ri.delay_on = (r - 1 >= D);
         rinfo[threadIdx.x] = ri;
     }
-    // the tables of the far region for this block: q = r - j in [qa, qb]
-    const int64_t qa = ra - (R.hi - 1);
-    if (far) {
-        const int64_t n = (R.hi - R.lo) + (rb - ra);
-        for (int64_t t = threadIdx.x; t <= n; t += NT) {
-            const int64_t q = qa + t;
-            tblE[t] = et_at(b, q) - et_at(b, q + D);
-            tblF[t] = phi_at(b, q);
-        }
+    fill_pow(g.alpha, pw);
+    if (cone) {
+        fill_tables(b, D, 0, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab[0], tab[1], nullptr, 0, NT / 2);
+        fill_tables(b, D, 0, ra - D, P.cone_L0 + (rb - ra), tab[0] + TBL / 2, tab[1] + TBL / 2, nullptr, NT / 2,
+                    NT / 2);
+    } else {
+        fill_tables(b, D, far, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab[0], tab[1], (far || is_strip) ? nullptr : tab[2],
+                    0, NT);
     }
     __syncthreads();
 
@@ -443,58 +541,15 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
     W.w = win;
     W.lo = P.win_lo;
     W.row0 = ra;
-    W.on = (is_strip && w == 0);
-    const int write_win = W.on && (P.cone_mode == 0);
-    const int cone = W.on && (P.cone_mode == 1);
 
-    if (cone) {
-        // the cone at the strip's right end, for every row of the block but
-        // the last: fills the window before the strip's own columns need it
-        Range C;
-        C.lo = D + 1 - P.cone_L0;
-        C.hi = D + 1;
-        C.own_lo = D + 1;                        // nothing owned
-        C.exact = 0;
-        Win Wc = W;
-        Wc.on = 0;                               // the cone's mirror reads are older than the block
-        Lane Lc;
-        load_base(g, b, C, Lc, ra);
-        const int64_t rc_end = (ra + P.T - 2 < rb) ? ra + P.T - 2 : rb;
-        for (int64_t r = ra; r <= rc_end; ++r) {
-            const int tau = (int)(r - ra);
-            const int64_t act = C.lo + (int64_t)H1 * tau;
-            do_row<false>(g, b, Wc, pw, C, Lc, wave_tot, tblE, tblF, qa, rinfo[tau], r, rc_end, act, tau & 1,
-                          0, 0, 0);
-            const int64_t j0 = C.lo + (int64_t)threadIdx.x * K;
-            #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int64_t j = j0 + i;
-                if (j >= W.lo && j <= D && j >= act) win[tau][j - W.lo] = Lc.up[i];
-            }
-        }
-        __syncthreads();
-    }
-
-    Lane L;
-    load_base(g, b, R, L, ra);
-    for (int64_t r = ra; r <= rb; ++r) {
-        const int tau = (int)(r - ra);
-        const int par = tau & 1;
-        const int64_t act = R.exact ? R.lo : R.own_lo - (int64_t)H1 * (P.T - tau) + 1;
-        const RowInfo ri = rinfo[tau];
-        double pe = far ? do_row<true>(g, b, W, pw, R, L, wave_tot, tblE, tblF, qa, ri, r, rb, act, par, 1, 0, 0)
-                        : do_row<false>(g, b, W, pw, R, L, wave_tot, tblE, tblF, qa, ri, r, rb, act, par, 1,
-                                        write_win, is_strip);
-        pe = wave_sum63(pe);
-        if ((threadIdx.x & 63) == 63) pe_lds[tau][threadIdx.x >> 6] = pe;
-        if (write_win) __syncthreads();          // the window row written above is read by the next row
-    }
+    if (far) march_rows<true>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win);
+    else march_rows<false>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
         const int64_t r = ra + tau;
         double tot = 0.0;
-        for (int w2 = 0; w2 < NW; ++w2) tot += pe_lds[tau][w2];
+        for (int w2 = 0; w2 < (cone ? NW / 2 : NW); ++w2) tot += pe_lds[tau][w2];
         if (is_strip && w == 0) {
             const cd v0 = b.Phi[r] * b.Et[r];
             tot += 0.5 * norm2(v0);
@@ -562,6 +617,8 @@ int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n)
                 P.strip_w = (D + Gs - 1) / Gs;
                 P.Gs = (int)((D + P.strip_w - 1) / P.strip_w);
                 if (P.strip_w + 1 - P.hmax < T) break;            // halo mirror reads must be older than the block
+                // the strip's first workgroup holds its columns and the cone in one half each
+                if (P.strip_w > (BM_THREADS / 2) * BM_K || P.cone_L0 > (BM_THREADS / 2) * BM_K) break;
                 if (D - (int64_t)(P.Gs - 1) * P.strip_w + P.hmax > BM_CAP) break;
             } else {
                 break;
