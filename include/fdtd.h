@@ -20,9 +20,11 @@
  * Memory.  The caller allocates and owns every device buffer: it passes one
  * device workspace of at least fdtd_workspace_size() bytes, which must stay
  * alive and untouched until fdtd_destroy().  The context holds views only.
- * Inside, the march keeps a ring of D+2 rows (the delay term reaches back
- * D+1 rows; every older value it needs lies in x <= -a and comes from the
- * exact solution), so memory does not grow with Nt.
+ * Inside, the march keeps a ring of D+2T+2 rows (the delay term reaches back
+ * D+1 rows, every older value it needs lies in x <= -a and comes from the
+ * exact solution; T <= 32 is the block of rows one launch marches, and the
+ * strip -a < x <= a runs one block ahead), plus a copy of the strip stored
+ * along anti-diagonals, so memory does not grow with Nt.
  *
  * Streams.  Every call enqueues its work on the HIP stream given to
  * fdtd_init and returns without waiting, except where stated.  A context is
@@ -142,6 +144,65 @@ int fdtd_describe(const fdtd_params *p, char *buf, size_t n);
  * last failed fdtd_init / fdtd_workspace_size when ctx is NULL). */
 const char *fdtd_strerror(int status);
 const char *fdtd_last_error(const fdtd_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Batches: n independent instances (each with its own grid, emitter and
+ * packet) marched together from row 0 to their own Nt.  Every kernel launch
+ * advances each instance that is not finished by one block of rows, so one
+ * launch carries the whole batch; the launch sequence is captured in a HIP
+ * graph at the first fdtd_batch_march and replayed afterwards.  Results per
+ * instance match the one-instance march to rounding (the batch uses wider
+ * workgroups, which changes only the truncation of the within-row recurrence
+ * below 2^-60 relative).
+ * ------------------------------------------------------------------------ */
+typedef struct fdtd_batch fdtd_batch;
+
+typedef struct fdtd_batch_opts {
+    uint32_t struct_size;   /* sizeof(fdtd_batch_opts) */
+    int32_t tmax;           /* largest block of rows per launch, 1..32 (0: 32) */
+    int64_t wmax;           /* widest column range of one workgroup (0: the most one holds, 1536) */
+    int32_t use_graph;      /* 1: capture the launch sequence in a HIP graph and replay it; 0: plain launches */
+    int32_t reserved;       /* must be 0 */
+} fdtd_batch_opts;
+
+/* Device workspace for the batch p[0..n-1] with these options (NULL: the
+ * defaults, tmax 32, widest workgroups, graph on). */
+int fdtd_batch_workspace_size(const fdtd_params *p, int32_t n, const fdtd_batch_opts *opts, size_t *bytes);
+
+/* Set up the batch in the caller's workspace (device pointer, 256-byte
+ * aligned, at least fdtd_batch_workspace_size bytes, owned by the caller and
+ * untouched until fdtd_batch_destroy) on the given HIP stream.  Every
+ * instance is validated as by fdtd_init; the first failure is reported with
+ * its index.  Enqueues the clearing of every ring and waits for it. */
+int fdtd_batch_init(const fdtd_params *p, int32_t n, const fdtd_batch_opts *opts, void *d_workspace, size_t bytes,
+                    void *hip_stream, fdtd_batch **out);
+
+/* Boundary tables of every instance (as fdtd_set_boundary); waits for them
+ * and reports the first instance whose gamma series failed. */
+int fdtd_batch_set_boundary(fdtd_batch *b);
+
+/* March every instance from row 0 to its Nt (FDTD_ESTATE unless the boundary
+ * was set since the last march).  Returns after enqueueing. */
+int fdtd_batch_march(fdtd_batch *b);
+
+/* fdtd_readout for instance i (0-based, the caller's order). */
+int fdtd_batch_readout(fdtd_batch *b, int32_t i, int32_t what, int64_t arg, void *dst, int64_t count,
+                       int32_t dst_on_device);
+
+/* Launches of one march, and workgroups of the first (largest) launch. */
+int fdtd_batch_info(const fdtd_batch *b, int64_t *launches, int64_t *max_workgroups);
+
+int fdtd_batch_sync(fdtd_batch *b);
+int fdtd_batch_destroy(fdtd_batch *b);   /* frees host state and the graph, not the workspace; accepts NULL */
+const char *fdtd_batch_last_error(const fdtd_batch *b);
+
+/* Autotuner: try each candidate (tmax in {32, 16, 8}, wmax in {1536, 768})
+ * whose workspace fits in `bytes`, march the first probe_rows rows of every
+ * instance with plain launches, time them with HIP events on the stream, and
+ * return the fastest candidate in *best (graph on) and its cell updates per
+ * second in *best_rate.  Uses and overwrites the workspace; synchronous. */
+int fdtd_batch_autotune(const fdtd_params *p, int32_t n, void *d_workspace, size_t bytes, void *hip_stream,
+                        int64_t probe_rows, fdtd_batch_opts *best, double *best_rate);
 
 #ifdef __cplusplus
 }

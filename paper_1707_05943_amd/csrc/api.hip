@@ -45,9 +45,9 @@ static int halo_for(cd alpha)
     return h < 1.0 ? 1 : (int)h;
 }
 
-static int plan_for(const fdtd_params* p, Plan* P, char* why, size_t n);
+static int plan_for(const fdtd_params* p, const PlanKnobs& kn, Plan* P, char* why, size_t n);
 
-static int validate(const fdtd_params* p, char* why, size_t n)
+int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
 {
     if (!p) { snprintf(why, n, "params is NULL"); return FDTD_EINVAL; }
     if (p->abi_version != FDTD_ABI_VERSION || p->struct_size != sizeof(fdtd_params)) {
@@ -84,8 +84,10 @@ static int validate(const fdtd_params* p, char* why, size_t n)
         return FDTD_EINVAL;
     }
     Plan P;
-    return plan_for(p, &P, why, n);
+    return plan_for(p, kn, &P, why, n);
 }
+
+static int validate(const fdtd_params* p, char* why, size_t n) { return ctx_validate(p, SOLO_KNOBS, why, n); }
 
 struct Layout {
     int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, total;
@@ -116,47 +118,42 @@ static Layout layout(const fdtd_params* p, const Plan& P)
     return L;
 }
 
-static int plan_for(const fdtd_params* p, Plan* P, char* why, size_t n)
+static int plan_for(const fdtd_params* p, const PlanKnobs& kn, Plan* P, char* why, size_t n)
 {
     Geom g;
     coefficients(p, &g);
-    return make_plan(p, halo_for(g.alpha), P, why, n);
+    return make_plan(p, halo_for(g.alpha), kn, P, why, n);
 }
 
-extern "C" {
-
-int fdtd_workspace_size(const fdtd_params* p, size_t* bytes)
+int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn)
 {
     char why[256];
-    int rc = validate(p, why, sizeof why);
-    if (rc) return fail(nullptr, rc, "%s", why);
-    if (!bytes) return fail(nullptr, FDTD_EINVAL, "bytes is NULL");
     Plan P;
-    plan_for(p, &P, why, sizeof why);
-    *bytes = (size_t)layout(p, P).total;
-    return FDTD_OK;
+    if (plan_for(p, kn, &P, why, sizeof why)) return -1;
+    return layout(p, P).total;
 }
 
-int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_stream, fdtd_ctx** out)
+int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes, hipStream_t stream,
+               fdtd_ctx** out, char* why, size_t nwhy)
 {
-    char why[256];
-    int rc = validate(p, why, sizeof why);
-    if (rc) return fail(nullptr, rc, "%s", why);
-    if (!out) return fail(nullptr, FDTD_EINVAL, "out is NULL");
+    int rc = ctx_validate(p, kn, why, nwhy);
+    if (rc) return rc;
+    if (!out) { snprintf(why, nwhy, "out is NULL"); return FDTD_EINVAL; }
     *out = nullptr;
     Plan P;
-    plan_for(p, &P, why, sizeof why);
+    plan_for(p, kn, &P, why, nwhy);
     const int64_t nblk = P.nwg;
     Layout L = layout(p, P);
-    if (!d_workspace || bytes < (size_t)L.total)
-        return fail(nullptr, FDTD_ESIZE, "workspace of %zu bytes is smaller than the %lld needed", bytes,
-                    (long long)L.total);
-    if (((uintptr_t)d_workspace) & 255) return fail(nullptr, FDTD_EINVAL, "workspace must be 256-byte aligned");
+    if (!d_workspace || bytes < (size_t)L.total) {
+        snprintf(why, nwhy, "workspace of %zu bytes is smaller than the %lld needed", bytes, (long long)L.total);
+        return FDTD_ESIZE;
+    }
+    if (((uintptr_t)d_workspace) & 255) { snprintf(why, nwhy, "workspace must be 256-byte aligned"); return FDTD_EINVAL; }
 
     fdtd_ctx* c = (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx));
-    if (!c) return fail(nullptr, FDTD_EDEVICE, "out of host memory");
+    if (!c) { snprintf(why, nwhy, "out of host memory"); return FDTD_EDEVICE; }
     c->p = *p;
-    c->stream = (hipStream_t)hip_stream;
+    c->stream = stream;
     c->nblk = nblk;
     c->plan = P;
     Geom& g = c->g;
@@ -194,8 +191,50 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     c->strip_row = -1;
     c->boundary_ready = 0;
     rc = launch_clear(c);
-    if (rc) { free(c); return fail(nullptr, rc, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError())); }
+    if (rc) {
+        free(c);
+        snprintf(why, nwhy, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError()));
+        return rc;
+    }
     *out = c;
+    return FDTD_OK;
+}
+
+int ctx_boundary_enqueue(fdtd_ctx* c)
+{
+    c->boundary_ready = 0;
+    int rc = launch_boundary(c, 0);
+    if (rc) return fail(c, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return FDTD_OK;
+}
+
+int ctx_boundary_status(fdtd_ctx* c, int st)
+{
+    if (st & STATUS_GAMMA_RANGE) return fail(c, FDTD_ERANGE, "gamma(n,z) series out of range");
+    if (st & STATUS_NONFINITE) return fail(c, FDTD_ERANGE, "non-finite boundary value");
+    c->row = 0;
+    c->strip_row = 0;
+    c->boundary_ready = 1;
+    return FDTD_OK;
+}
+
+extern "C" {
+
+int fdtd_workspace_size(const fdtd_params* p, size_t* bytes)
+{
+    char why[256];
+    int rc = validate(p, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    if (!bytes) return fail(nullptr, FDTD_EINVAL, "bytes is NULL");
+    *bytes = (size_t)ctx_bytes(p, SOLO_KNOBS);
+    return FDTD_OK;
+}
+
+int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_stream, fdtd_ctx** out)
+{
+    char why[256];
+    int rc = ctx_create(p, SOLO_KNOBS, d_workspace, bytes, (hipStream_t)hip_stream, out, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
     return FDTD_OK;
 }
 
@@ -357,7 +396,7 @@ int fdtd_describe(const fdtd_params* p, char* buf, size_t n)
     if (rc) return fail(nullptr, rc, "%s", why);
     if (!buf || n == 0) return fail(nullptr, FDTD_EINVAL, "buf is NULL");
     Plan P;
-    plan_for(p, &P, why, sizeof why);
+    plan_for(p, SOLO_KNOBS, &P, why, sizeof why);
     Geom g;
     coefficients(p, &g);
     snprintf(buf, n,

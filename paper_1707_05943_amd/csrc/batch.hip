@@ -1,0 +1,390 @@
+// Batched marches: many independent instances of Eq. (1), each with its own
+// grid (Nx, D, Delta) and packet, advanced together.  Launch k of the batch
+// runs launch k of every instance that still needs one (block_rows), so one
+// kernel launch carries hundreds of instances; the whole launch sequence is
+// captured once in a HIP graph and replayed.  The autotuner below picks the
+// row-block cap and the workgroup width by timing a prefix of the march.
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "fdtd_common.h"
+
+struct fdtd_batch {
+    int n = 0;
+    std::vector<fdtd_ctx*> c;        // per instance, in the caller's order
+    std::vector<int> order;          // instance ids, most launches first
+    std::vector<BInst> h_tab;        // device table contents (sorted order)
+    BInst* d_tab = nullptr;          // in the workspace
+    std::vector<int> n_active;       // per launch k: instances still marching
+    std::vector<int> nb;             // per launch k: workgroups launched (multiple of 8)
+    int64_t Lmax = 0;
+    hipStream_t stream = nullptr;    // the caller's stream
+    hipStream_t cap = nullptr;       // private stream the graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    fdtd_batch_opts o;
+    int state = 0;                   // 0: no boundary, 1: ready to march, 2: marched
+    char err[512];
+};
+
+static char g_berr[512];
+
+static int bfail(fdtd_batch* b, int code, const char* fmt, ...)
+{
+    char* dst = b ? b->err : g_berr;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(dst, 512, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static int64_t al256(int64_t n) { return (n + 255) & ~(int64_t)255; }
+
+static int opts_check(const fdtd_batch_opts* o, fdtd_batch_opts* out, char* why, size_t n)
+{
+    fdtd_batch_opts d;
+    memset(&d, 0, sizeof d);
+    d.struct_size = sizeof(fdtd_batch_opts);
+    d.tmax = BM_TMAX;
+    d.wmax = BM_CAP;
+    d.use_graph = 1;
+    if (o) {
+        if (o->struct_size != sizeof(fdtd_batch_opts)) {
+            snprintf(why, n, "opts struct_size %u, expected %zu", o->struct_size, sizeof(fdtd_batch_opts));
+            return FDTD_EINVAL;
+        }
+        if (o->tmax < 0 || o->tmax > BM_TMAX) { snprintf(why, n, "tmax must be 0..%d", BM_TMAX); return FDTD_EINVAL; }
+        if (o->wmax < 0) { snprintf(why, n, "wmax must be >= 0"); return FDTD_EINVAL; }
+        if (o->use_graph != 0 && o->use_graph != 1) { snprintf(why, n, "use_graph must be 0 or 1"); return FDTD_EINVAL; }
+        if (o->tmax) d.tmax = o->tmax;
+        if (o->wmax) d.wmax = o->wmax < BM_CAP ? o->wmax : BM_CAP;
+        d.use_graph = o->use_graph;
+    }
+    *out = d;
+    return FDTD_OK;
+}
+
+static PlanKnobs knobs_of(const fdtd_batch_opts& o)
+{
+    PlanKnobs k;
+    k.ncu = 1;              // the widest workgroups: the batch, not one instance, fills the chip
+    k.tmax = o.tmax;
+    k.wmax = o.wmax;
+    return k;
+}
+
+static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o, int64_t* total, char* why,
+                       size_t nwhy)
+{
+    const PlanKnobs kn = knobs_of(o);
+    int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst));
+    for (int i = 0; i < n; ++i) {
+        int rc = ctx_validate(&p[i], kn, why, nwhy);
+        if (rc) {
+            char tmp[256];
+            snprintf(tmp, sizeof tmp, "instance %d: %s", i, why);
+            snprintf(why, nwhy, "%s", tmp);
+            return rc;
+        }
+        t += al256(ctx_bytes(&p[i], kn));
+    }
+    *total = t;
+    return FDTD_OK;
+}
+
+static void destroy(fdtd_batch* b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (fdtd_ctx* c : b->c) fdtd_destroy(c);
+    delete b;
+}
+
+// the launches of the batch from launch k0 to k1-1 on stream s
+static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
+{
+    for (int64_t k = k0; k < k1 && k < b->Lmax; ++k) {
+        int rc = launch_block_batch(b->d_tab, b->n_active[k], k, b->nb[k], s);
+        if (rc) return rc;
+    }
+    return FDTD_OK;
+}
+
+extern "C" {
+
+int fdtd_batch_workspace_size(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts, size_t* bytes)
+{
+    char why[320];
+    if (!p || n < 1 || !bytes) return bfail(nullptr, FDTD_EINVAL, "params, n >= 1 and bytes are required");
+    fdtd_batch_opts o;
+    int rc = opts_check(opts, &o, why, sizeof why);
+    if (rc) return bfail(nullptr, rc, "%s", why);
+    int64_t t = 0;
+    rc = batch_bytes(p, n, o, &t, why, sizeof why);
+    if (rc) return bfail(nullptr, rc, "%s", why);
+    *bytes = (size_t)t;
+    return FDTD_OK;
+}
+
+int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts, void* d_workspace, size_t bytes,
+                    void* hip_stream, fdtd_batch** out)
+{
+    char why[320];
+    if (!out) return bfail(nullptr, FDTD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p || n < 1) return bfail(nullptr, FDTD_EINVAL, "params and n >= 1 are required");
+    fdtd_batch_opts o;
+    int rc = opts_check(opts, &o, why, sizeof why);
+    if (rc) return bfail(nullptr, rc, "%s", why);
+    int64_t total = 0;
+    rc = batch_bytes(p, n, o, &total, why, sizeof why);
+    if (rc) return bfail(nullptr, rc, "%s", why);
+    if (!d_workspace || bytes < (size_t)total)
+        return bfail(nullptr, FDTD_ESIZE, "workspace of %zu bytes is smaller than the %lld needed", bytes,
+                     (long long)total);
+    if (((uintptr_t)d_workspace) & 255) return bfail(nullptr, FDTD_EINVAL, "workspace must be 256-byte aligned");
+
+    fdtd_batch* b = new fdtd_batch();
+    b->n = n;
+    b->o = o;
+    b->stream = (hipStream_t)hip_stream;
+    const PlanKnobs kn = knobs_of(o);
+    char* base = (char*)d_workspace;
+    b->d_tab = (BInst*)base;
+    int64_t off = al256((int64_t)n * (int64_t)sizeof(BInst));
+    for (int i = 0; i < n; ++i) {
+        const int64_t sz = ctx_bytes(&p[i], kn);
+        fdtd_ctx* c = nullptr;
+        rc = ctx_create(&p[i], kn, base + off, (size_t)sz, b->stream, &c, why, sizeof why);
+        if (rc) {
+            destroy(b);
+            return bfail(nullptr, rc, "instance %d: %s", i, why);
+        }
+        b->c.push_back(c);
+        off += al256(sz);
+    }
+
+    // sort by launch count, most first: the instances active in launch k are then a prefix
+    std::vector<int64_t> L(n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t T = b->c[i]->plan.T, Nt = b->c[i]->p.Nt;
+        L[i] = 1 + (Nt + T - 1) / T;
+        b->order.push_back(i);
+    }
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return L[x] > L[y]; });
+    b->Lmax = L[b->order[0]];
+    int64_t wg = 0;
+    std::vector<int64_t> wg_end(n);
+    for (int q = 0; q < n; ++q) {
+        const fdtd_ctx* c = b->c[b->order[q]];
+        BInst e;
+        memset(&e, 0, sizeof e);
+        e.g = c->g;
+        e.b = c->b;
+        e.P = c->plan;
+        e.wg_begin = wg;
+        e.launches = L[b->order[q]];
+        wg += c->plan.nwg;
+        wg_end[q] = wg;
+        b->h_tab.push_back(e);
+    }
+    b->n_active.resize(b->Lmax);
+    b->nb.resize(b->Lmax);
+    int q = n;
+    for (int64_t k = 0; k < b->Lmax; ++k) {
+        while (q > 0 && b->h_tab[q - 1].launches <= k) --q;
+        b->n_active[k] = q;
+        const int64_t w = wg_end[q - 1];
+        if (w > (int64_t)0x7fffffff - 8) {
+            destroy(b);
+            return bfail(nullptr, FDTD_EINVAL, "too many workgroups in one launch");
+        }
+        b->nb[k] = (int)(((w + 7) / 8) * 8);
+    }
+    hipError_t e = hipMemcpyAsync(b->d_tab, b->h_tab.data(), (size_t)n * sizeof(BInst), hipMemcpyHostToDevice,
+                                  b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        destroy(b);
+        return bfail(nullptr, FDTD_EDEVICE, "copy of the instance table failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return FDTD_OK;
+}
+
+int fdtd_batch_set_boundary(fdtd_batch* b)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    b->state = 0;
+    for (int i = 0; i < b->n; ++i) {
+        int rc = ctx_boundary_enqueue(b->c[i]);
+        if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(b->c[i]));
+    }
+    std::vector<int> st(b->n, 0);
+    for (int i = 0; i < b->n; ++i) {
+        hipError_t e = hipMemcpyAsync(&st[i], b->c[i]->b.status, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "status copy failed: %s", hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "boundary kernels failed: %s", hipGetErrorString(e));
+    for (int i = 0; i < b->n; ++i) {
+        int rc = ctx_boundary_status(b->c[i], st[i]);
+        if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(b->c[i]));
+    }
+    b->state = 1;
+    return FDTD_OK;
+}
+
+int fdtd_batch_march(fdtd_batch* b)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    if (b->state != 1) return bfail(b, FDTD_ESTATE, "march needs a fresh boundary (fdtd_batch_set_boundary)");
+    if (b->o.use_graph) {
+        if (!b->exec) {
+            hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            int rc = enqueue(b, 0, b->Lmax, b->cap);
+            e = hipStreamEndCapture(b->cap, &b->graph);
+            if (rc || e != hipSuccess)
+                return bfail(b, FDTD_EDEVICE, "graph capture failed: %s", hipGetErrorString(hipGetLastError()));
+            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                b->exec = nullptr;
+                return bfail(b, FDTD_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+            }
+        }
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
+    } else {
+        int rc = enqueue(b, 0, b->Lmax, b->stream);
+        if (rc) return bfail(b, rc, "march launch failed: %s", hipGetErrorString(hipGetLastError()));
+    }
+    for (fdtd_ctx* c : b->c) {
+        c->row = c->p.Nt;
+        c->strip_row = c->p.Nt;
+    }
+    b->state = 2;
+    return FDTD_OK;
+}
+
+int fdtd_batch_readout(fdtd_batch* b, int32_t i, int32_t what, int64_t arg, void* dst, int64_t count,
+                       int32_t dst_on_device)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    if (i < 0 || i >= b->n) return bfail(b, FDTD_EINVAL, "instance %d out of 0..%d", i, b->n - 1);
+    int rc = fdtd_readout(b->c[i], what, arg, dst, count, dst_on_device);
+    if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(b->c[i]));
+    return FDTD_OK;
+}
+
+int fdtd_batch_info(const fdtd_batch* b, int64_t* launches, int64_t* max_workgroups)
+{
+    if (!b) return FDTD_EINVAL;
+    if (launches) *launches = b->Lmax;
+    if (max_workgroups) *max_workgroups = b->nb.empty() ? 0 : b->nb[0];
+    return FDTD_OK;
+}
+
+int fdtd_batch_sync(fdtd_batch* b)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "%s", hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+int fdtd_batch_destroy(fdtd_batch* b)
+{
+    destroy(b);
+    return FDTD_OK;
+}
+
+const char* fdtd_batch_last_error(const fdtd_batch* b) { return b ? b->err : g_berr; }
+
+// Autotuner: for each candidate (row-block cap, workgroup width cap) that
+// fits the workspace, set up the batch, march its first probe_rows rows with
+// plain launches and time them with events; the candidate with the most cell
+// updates per second wins (graph capture is switched on in the result).
+int fdtd_batch_autotune(const fdtd_params* p, int32_t n, void* d_workspace, size_t bytes, void* hip_stream,
+                        int64_t probe_rows, fdtd_batch_opts* best, double* best_rate)
+{
+    if (!p || n < 1 || !best || probe_rows < 1) return bfail(nullptr, FDTD_EINVAL, "bad arguments");
+    static const int tmaxes[] = {32, 16, 8};
+    static const int64_t wmaxes[] = {BM_CAP, 768};
+    double top = -1.0;
+    fdtd_batch_opts win;
+    memset(&win, 0, sizeof win);
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return bfail(nullptr, FDTD_EDEVICE, "event creation failed");
+    int rc = FDTD_OK;
+    for (int tm : tmaxes) {
+        for (int64_t wm : wmaxes) {
+            fdtd_batch_opts o;
+            memset(&o, 0, sizeof o);
+            o.struct_size = sizeof o;
+            o.tmax = tm;
+            o.wmax = wm;
+            o.use_graph = 0;
+            size_t need = 0;
+            if (fdtd_batch_workspace_size(p, n, &o, &need) != FDTD_OK || need > bytes) continue;
+            fdtd_batch* b = nullptr;
+            rc = fdtd_batch_init(p, n, &o, d_workspace, bytes, hip_stream, &b);
+            if (rc) break;
+            rc = fdtd_batch_set_boundary(b);
+            if (rc) { destroy(b); break; }
+            // launches that cover probe_rows rows of every instance, and the cells they update
+            int64_t k1 = 0;
+            double cells = 0.0;
+            for (const BInst& e : b->h_tab) {
+                const int64_t rows = probe_rows < e.g.Nt ? probe_rows : e.g.Nt;
+                const int64_t k = 1 + (rows + e.P.T - 1) / e.P.T;
+                if (k > k1) k1 = k;
+            }
+            if (k1 > b->Lmax) k1 = b->Lmax;
+            for (const BInst& e : b->h_tab) {
+                for (int64_t k = 0; k < k1 && k < e.launches; ++k) {
+                    int64_t m0, m1, s0, s1;
+                    block_rows(e.P.T, e.g.Nt, k, &m0, &m1, &s0, &s1);
+                    if (m1 >= m0) cells += (double)(m1 - m0 + 1) * (double)(e.g.Nx - e.g.D);
+                    if (s1 >= s0) cells += (double)(s1 - s0 + 1) * (double)e.g.D;
+                }
+            }
+            (void)hipEventRecord(e0, s);
+            rc = enqueue(b, 0, k1, s);
+            (void)hipEventRecord(e1, s);
+            hipError_t he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            destroy(b);
+            if (rc || he != hipSuccess) { rc = FDTD_EDEVICE; break; }
+            const double rate = cells / (ms * 1e-3);
+            if (rate > top) {
+                top = rate;
+                win = o;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return bfail(nullptr, rc, "autotune failed: %s", g_berr[0] ? g_berr : "device error");
+    if (top < 0.0) return bfail(nullptr, FDTD_ESIZE, "no candidate fits the workspace");
+    win.use_graph = 1;
+    *best = win;
+    if (best_rate) *best_rate = top;
+    return FDTD_OK;
+}
+
+}  // extern "C"

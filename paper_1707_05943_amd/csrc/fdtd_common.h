@@ -139,5 +139,54 @@ constexpr int BM_K = 3;
 constexpr int BM_CAP = BM_THREADS * BM_K;      // columns a workgroup can hold in one row
 constexpr int BM_TMAX = 32;                    // largest block of rows (LDS window is BM_TMAX x BM_TMAX)
 
-int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n);
+// Planner knobs: workgroups the instance should spread over (about one per
+// compute unit when it runs alone), the largest block of rows, and the widest
+// column range of one workgroup.
+struct PlanKnobs {
+    int ncu;
+    int tmax;
+    int64_t wmax;
+};
+constexpr PlanKnobs SOLO_KNOBS = {256, BM_TMAX, BM_CAP};
+
+int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char* why, size_t n);
 int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1);
+
+// Rows of launch k of a march that starts at row 0, blocks being rows
+// [1 + iT, (i+1)T]: launch 0 marches the strip's first block alone, launch
+// k >= 1 the outgoing region over block k-1 and the strip over block k.  A
+// march of Nt rows takes 1 + ceil(Nt / T) launches.  Empty ranges have
+// m1 < m0 or s1 < s0.
+__host__ __device__ inline void block_rows(int64_t T, int64_t Nt, int64_t k, int64_t* m0, int64_t* m1, int64_t* s0,
+                                           int64_t* s1)
+{
+    if (k == 0) {
+        *m0 = 1;
+        *m1 = 0;
+    } else {
+        *m0 = 1 + (k - 1) * T;
+        *m1 = (k * T < Nt) ? k * T : Nt;
+    }
+    *s0 = 1 + k * T;
+    *s1 = ((k + 1) * T < Nt) ? (k + 1) * T : Nt;
+}
+
+// One instance of a batched launch (device table, sorted by `launches`,
+// largest first).
+struct BInst {
+    Geom g;
+    Bufs b;
+    Plan P;
+    int64_t wg_begin;    // first workgroup of this instance in a launch
+    int64_t launches;    // 1 + ceil(Nt / T)
+};
+
+int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipStream_t s);
+
+// Internal context life cycle, shared by the one-instance and batched ABIs.
+int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn);
+int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n);
+int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_ws, size_t bytes, hipStream_t s, fdtd_ctx** out,
+               char* why, size_t n);
+int ctx_boundary_enqueue(fdtd_ctx* c);          // boundary kernels without waiting
+int ctx_boundary_status(fdtd_ctx* c, int st);    // turn the device status word into an error (sets c->err)

@@ -434,18 +434,27 @@ __device__ __forceinline__ void march_rows(const Geom& g, const Bufs& b, const W
     }
 }
 
-__global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
-                                                       int64_t s0, int64_t s1)
-{
-    __shared__ cd wave_tot[2][NW];
-    __shared__ double pe_lds[BM_TMAX][NW];
-    __shared__ cd win[BM_TMAX][BM_TMAX];
-    __shared__ cd tab[3][TBL];
-    __shared__ RowInfo rinfo[BM_TMAX];
-    __shared__ Pow pw;
+struct Shared {
+    cd wave_tot[2][NW];
+    double pe_lds[BM_TMAX][NW];
+    cd win[BM_TMAX][BM_TMAX];
+    cd tab[3][TBL];
+    RowInfo rinfo[BM_TMAX];
+    Pow pw;
+};
 
-    const int bid = blockIdx.x;
-    const int w = (bid % 8) * (P.nb / 8) + bid / 8;     // neighbouring column ranges share an XCD
+// Workgroup w of an instance's launch: the outgoing region over rows m0..m1
+// and the strip over rows s0..s1 (either range may be empty).
+__device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const Plan& P, int64_t m0, int64_t m1,
+                                           int64_t s0, int64_t s1, int w, Shared& sh)
+{
+    cd(*wave_tot)[NW] = sh.wave_tot;
+    double(*pe_lds)[NW] = sh.pe_lds;
+    cd(*win)[BM_TMAX] = sh.win;
+    cd(*tab)[TBL] = sh.tab;
+    RowInfo* rinfo = sh.rinfo;
+    Pow& pw = sh.pw;
+
     if (w >= P.nwg) return;
     const int is_strip = w < P.Gs;
     const int64_t ra = is_strip ? s0 : m0;
@@ -558,6 +567,38 @@ __global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, in
     }
 }
 
+__global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
+                                                       int64_t s0, int64_t s1)
+{
+    __shared__ Shared sh;
+    const int bid = blockIdx.x;
+    const int w = (bid % 8) * (P.nb / 8) + bid / 8;     // neighbouring column ranges share an XCD
+    block_body(g, b, P, m0, m1, s0, s1, w, sh);
+}
+
+// Many instances in one launch: launch k advances every instance whose march
+// needs more than k launches (a prefix of the table, which is sorted by that
+// count) by one block.  Workgroup ids are laid out instance after instance
+// (tab[i].wg_begin) and dealt to the XCDs in contiguous runs, as above.
+__global__ __launch_bounds__(BM_THREADS) void k_block_batch(const BInst* __restrict__ tab, int n_active, int64_t k,
+                                                             int nb)
+{
+    __shared__ Shared sh;
+    const int bid = blockIdx.x;
+    const int64_t wgl = (int64_t)(bid % 8) * (nb / 8) + bid / 8;
+    int lo = 0, hi = n_active - 1;
+    while (lo < hi) {                                    // last instance with wg_begin <= wgl
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].wg_begin <= wgl) lo = mid; else hi = mid - 1;
+    }
+    const BInst& e = tab[lo];
+    const int w = (int)(wgl - e.wg_begin);
+    if (w >= e.P.nwg || k >= e.launches) return;
+    int64_t m0, m1, s0, s1;
+    block_rows(e.P.T, e.g.Nt, k, &m0, &m1, &s0, &s1);
+    block_body(e.g, e.b, e.P, m0, m1, s0, s1, w, sh);
+}
+
 }  // namespace
 
 int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1)
@@ -566,26 +607,36 @@ int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1)
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
+int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_block_batch, dim3(nb), dim3(BM_THREADS), 0, s, d_tab, n_active, k, nb);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
 // Planner: rows per block T, halo, and the split of the columns into
 // workgroups of about equal cost (columns with mirror reads -- the strip and
 // the near part of the outgoing region -- count MIRROR_COST times a far
-// column), about one workgroup per compute unit.
+// column), about kn.ncu workgroups (one per compute unit for an instance that
+// runs alone; an instance of a batch asks for the widest workgroups).
 static const double MIRROR_COST = 2.0;
-static const int NCU = 256;
 
-int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n)
+int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char* why, size_t n)
 {
     const int64_t D = p->D, Nx = p->Nx;
+    const int NCU = kn.ncu < 1 ? 1 : kn.ncu;
     const int targets[] = {32, 24, 16, 12, 8, 6, 4, 3, 2, 1};
     for (int T : targets) {
-        if (T > BM_TMAX || T > D) continue;
+        if (T > BM_TMAX || T > kn.tmax || T > D) continue;
         Plan P;
         memset(&P, 0, sizeof P);
         P.T = T;
         P.H = H;
         P.hmax = (H + 1) * T - 1;
-        const int64_t room = BM_CAP - P.hmax;           // owned columns a halo workgroup can hold
+        int64_t room = BM_CAP - P.hmax;                 // owned columns a halo workgroup can hold
         if (room < 64) continue;
+        // a narrower cap, but never below twice the halo
+        const int64_t cap = kn.wmax > 2 * (int64_t)P.hmax ? kn.wmax : 2 * (int64_t)P.hmax;
+        if (cap < room) room = cap;
         // the near part ends where far workgroups' halos hold no mirror reads
         P.near_end = 2 * D + P.hmax;
         if (P.near_end > Nx) P.near_end = Nx;
@@ -597,7 +648,7 @@ int make_plan(const fdtd_params* p, int H, Plan* out, char* why, size_t n)
         if (minw > room) minw = room;
         double budget = (MIRROR_COST * (double)(D + near_cols) + (double)far_cols) / NCU;
         int ok = 0;
-        for (int it = 0; it < 200; ++it, budget *= 1.02) {
+        for (int it = 0; it < 2000; ++it, budget *= 1.02) {
             int64_t wm = (int64_t)(budget / MIRROR_COST), wf = (int64_t)budget;
             if (wm < minw) wm = minw;
             if (wf < minw) wf = minw;

@@ -24,7 +24,10 @@ STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", 
 # every symbol include/fdtd.h declares
 EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_boundary_tables",
            "fdtd_march", "fdtd_current_row", "fdtd_readout", "fdtd_sync", "fdtd_destroy",
-           "fdtd_describe", "fdtd_strerror", "fdtd_last_error")
+           "fdtd_describe", "fdtd_strerror", "fdtd_last_error",
+           "fdtd_batch_workspace_size", "fdtd_batch_init", "fdtd_batch_set_boundary", "fdtd_batch_march",
+           "fdtd_batch_readout", "fdtd_batch_info", "fdtd_batch_sync", "fdtd_batch_destroy",
+           "fdtd_batch_last_error", "fdtd_batch_autotune")
 
 
 class FdtdParams(ctypes.Structure):
@@ -34,6 +37,16 @@ class FdtdParams(ctypes.Structure):
                 ("incident", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("k", ctypes.c_double), ("alpha", ctypes.c_double), ("x0", ctypes.c_double),
                 ("width", ctypes.c_double), ("phase", ctypes.c_double)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("tmax", ctypes.c_int32), ("wmax", ctypes.c_int64),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def batch_opts(tmax: int = 0, wmax: int = 0, use_graph: bool = True) -> BatchOpts:
+    return BatchOpts(struct_size=ctypes.sizeof(BatchOpts), tmax=int(tmax), wmax=int(wmax),
+                     use_graph=1 if use_graph else 0, reserved=0)
 
 
 class FdtdError(RuntimeError):
@@ -69,6 +82,18 @@ def load(path: str = LIB_PATH):
     lib.fdtd_strerror.restype = ctypes.c_char_p
     lib.fdtd_last_error.argtypes = [vp]
     lib.fdtd_last_error.restype = ctypes.c_char_p
+    BO = ctypes.POINTER(BatchOpts)
+    lib.fdtd_batch_workspace_size.argtypes = [P, i32, BO, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdtd_batch_init.argtypes = [P, i32, BO, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.fdtd_batch_set_boundary.argtypes = [vp]
+    lib.fdtd_batch_march.argtypes = [vp]
+    lib.fdtd_batch_readout.argtypes = [vp, i32, i32, i64, vp, i64, i32]
+    lib.fdtd_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.fdtd_batch_sync.argtypes = [vp]
+    lib.fdtd_batch_destroy.argtypes = [vp]
+    lib.fdtd_batch_last_error.argtypes = [vp]
+    lib.fdtd_batch_last_error.restype = ctypes.c_char_p
+    lib.fdtd_batch_autotune.argtypes = [P, i32, vp, ctypes.c_size_t, vp, i64, BO, ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -174,6 +199,127 @@ class Solver:
         if getattr(self, "ctx", None):
             self.lib.fdtd_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _param_array(instances):
+    arr = (FdtdParams * len(instances))()
+    for i, inst in enumerate(instances):
+        arr[i] = params(inst)
+    return arr
+
+
+def batch_workspace_size(instances, opts: BatchOpts | None = None) -> int:
+    lib = load()
+    arr = _param_array(instances)
+    n = ctypes.c_size_t(0)
+    rc = lib.fdtd_batch_workspace_size(arr, len(instances), ctypes.byref(opts) if opts else None, ctypes.byref(n))
+    if rc:
+        raise FdtdError(rc, lib.fdtd_batch_last_error(None).decode())
+    return int(n.value)
+
+
+def autotune(instances, probe_rows: int = 256, device: str = "cuda:0", workspace=None):
+    """Run the library's autotuner on this batch; returns (BatchOpts, cell updates/s of the winner)."""
+    import torch
+    lib = load()
+    arr = _param_array(instances)
+    dev = torch.device(device)
+    if workspace is None:
+        need = max(batch_workspace_size(instances, batch_opts(t, w)) for t in (32, 16, 8) for w in (0, 768))
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    best = BatchOpts()
+    rate = ctypes.c_double(0.0)
+    rc = lib.fdtd_batch_autotune(arr, len(instances), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                 ctypes.c_void_p(stream.cuda_stream), int(probe_rows), ctypes.byref(best),
+                                 ctypes.byref(rate))
+    if rc:
+        raise FdtdError(rc, lib.fdtd_batch_last_error(None).decode())
+    return best, float(rate.value)
+
+
+class Batch:
+    """Many instances marched together (one launch per row block for the whole batch)."""
+
+    def __init__(self, instances, opts: BatchOpts | None = None, device: str = "cuda:0", stream=None,
+                 workspace=None):
+        import torch
+        self.lib = load()
+        self.instances = list(instances)
+        self.n = len(self.instances)
+        self.arr = _param_array(self.instances)
+        self.opts = opts if opts is not None else batch_opts()
+        self.device = torch.device(device)
+        nbytes = batch_workspace_size(self.instances, self.opts)
+        if workspace is not None and workspace.numel() >= nbytes:
+            self.ws = workspace
+        else:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p(0)
+        rc = self.lib.fdtd_batch_init(self.arr, self.n, ctypes.byref(self.opts), ctypes.c_void_p(self.ws.data_ptr()),
+                                      self.ws.numel(), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc:
+            raise FdtdError(rc, self.lib.fdtd_batch_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc:
+            raise FdtdError(rc, self.lib.fdtd_batch_last_error(self.h).decode())
+
+    def set_boundary(self):
+        self._check(self.lib.fdtd_batch_set_boundary(self.h))
+        return self
+
+    def march(self):
+        self._check(self.lib.fdtd_batch_march(self.h))
+        return self
+
+    def info(self) -> dict:
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.lib.fdtd_batch_info(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return {"launches": int(a.value), "max_workgroups": int(b.value)}
+
+    def _ro(self, i, what, arg, count, dtype):
+        out = np.empty(count, dtype=dtype)
+        self._check(self.lib.fdtd_batch_readout(self.h, int(i), what, int(arg), out.ctypes.data_as(ctypes.c_void_p),
+                                                int(count), 0))
+        return out
+
+    def readout_device(self, i, what, arg, dst, count):
+        """readout into a device tensor (enqueued on the batch's stream)"""
+        self._check(self.lib.fdtd_batch_readout(self.h, int(i), what, int(arg), ctypes.c_void_p(dst.data_ptr()),
+                                                int(count), 1))
+
+    def _p(self, i):
+        # out-of-range indices go to the library, which reports them
+        return self.arr[i] if 0 <= i < self.n else FdtdParams(Nx=0, Nt=0)
+
+    def row_values(self, i: int, rho: int) -> np.ndarray:
+        return self._ro(i, RO_ROW, rho, self._p(i).Nx + 1, np.complex128)
+
+    def pe(self, i: int, count: int | None = None) -> np.ndarray:
+        return self._ro(i, RO_PE, 0, self._p(i).Nt + 1 if count is None else count, np.float64)
+
+    def chi(self, i: int, count: int) -> np.ndarray:
+        return self._ro(i, RO_CHI, 0, count, np.complex128)
+
+    def E(self, i: int) -> np.ndarray:
+        return self._ro(i, RO_E, 0, self._p(i).Nt + 1, np.complex128)
+
+    def sync(self):
+        self._check(self.lib.fdtd_batch_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fdtd_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -72,3 +72,24 @@ def test_strerror_texts():
     lib = fdtd.load()
     assert lib.fdtd_strerror(0) == b"ok"
     assert lib.fdtd_strerror(-2) == b"buffer too small"
+
+
+def test_batch_workspace_and_validation():
+    from paper_1707_05943_amd import workloads as W
+    cases = [W.tiny_gauss(D=10, Nx=300, Nt=100, seed=1), W.tiny_gauss(D=40, Nx=1025, Nt=200, seed=2)]
+    n_default = fdtd.batch_workspace_size(cases)
+    n_t8 = fdtd.batch_workspace_size(cases, fdtd.batch_opts(tmax=8))
+    assert n_default > 0 and n_t8 > 0
+    # a smaller row block needs fewer ring rows (D + 2T + 2)
+    assert n_t8 < n_default
+    bad = W.with_sizes(cases[1], Nx=20)            # Nx < D + 1
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.batch_workspace_size([cases[0], bad])
+    assert e.value.code == -1 and "instance 1" in str(e.value)
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.batch_workspace_size(cases, fdtd.batch_opts(tmax=64))
+    assert e.value.code == -1
+    o = fdtd.batch_opts()
+    o.struct_size = 8
+    with pytest.raises(fdtd.FdtdError):
+        fdtd.batch_workspace_size(cases, o)

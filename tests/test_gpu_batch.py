@@ -1,0 +1,157 @@
+"""GPU parity of the batched march: many heterogeneous instances in one
+launch sequence, against the CPU oracle per instance, with and without the
+captured HIP graph, and after the autotuner's choice."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_05943_amd import fdtd
+from paper_1707_05943_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+FLOOR = 0.1
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gauss(D, Nx, Nt, Delta, width, seed, k0a=0.5 * math.pi, x0w=6.0):
+    inst = W.tiny_gauss(D=D, Nx=Nx, Nt=Nt, Delta=Delta, width=width, seed=seed, k0a=k0a)
+    inst.x0 = -inst.a - x0w * width
+    return inst
+
+
+def batch_cases():
+    """different D (and so different rows per block), widths, lengths and
+    families; the instances finish after different numbers of launches"""
+    return [
+        _gauss(10, 2600, 300, 0.02, 0.5, 31),                 # T = 8, several workgroups
+        _gauss(40, 1025, 200, 0.025, 0.6, 32),                # T = 32
+        _gauss(2, 3, 50, 0.1, 0.4, 33),                       # Nx = D + 1, T = 2
+        _gauss(1200, 3100, 1400, 0.0025, 0.5, 34),            # strip wider than a workgroup
+        _gauss(24, 700, 900, 0.02, 0.7, 35, k0a=2.0),         # longest march
+        W.Instance(name="exp2_b", Nx=1500, D=24, Nt=400, Delta=0.02, omega0=2.0, Gamma=1.0,
+                   incident=W.INC_EXP2, k=2.3, alpha=0.8, x0=0.0, width=1.0, phase=0.9),
+        W.Instance(name="coarse_b", Nx=1500, D=24, Nt=300, Delta=0.5, omega0=4.5, Gamma=1.0,
+                   incident=W.INC_GAUSS2, k=4.5, x0=-6.0 - 8 * 3.0, width=3.0, phase=0.3),
+    ]
+
+
+def _oracle(inst):
+    """the oracle's run of `inst` with the row at the peak of P_e kept: rows
+    that have decayed below 10% of that row are measured against 10% of it
+    (the scheme's amplification factor is -1 at k Delta = pi, so grid-scale
+    rounding noise is not damped while the field decays)"""
+    E = oracle.E_table(inst)
+    pre = oracle.march(inst, E, want_ring=False)["pe"]
+    rp = int(np.argmax(pre)) if np.all(np.isfinite(pre)) else inst.Nt // 2
+    ref = oracle.march(inst, E, snap_rows=[max(1, rp)])
+    ref["scale"] = max([np.linalg.norm(ref["snaps"][0])] + [np.linalg.norm(v) for v in ref["ring"]])
+    return ref
+
+
+def _compare_instance(bat, i, inst, ref, label):
+    """last D+2 rows and P_e of instance i against the oracle run `ref`"""
+    scale = ref["scale"]
+    R = inst.D + 2
+    worst = 0.0
+    for q in range(R):
+        rho = inst.Nt - (R - 1) + q
+        if rho < 0:
+            continue
+        got = bat.row_values(i, rho)
+        e = np.linalg.norm(got - ref["ring"][q]) / max(np.linalg.norm(ref["ring"][q]), FLOOR * scale, 1e-300)
+        worst = max(worst, e)
+        assert e <= TOL, (label, inst.name, "row", rho, e)
+    if inst.incident != W.INC_PLANE:
+        pe = bat.pe(i)
+        e = np.linalg.norm(pe - ref["pe"]) / np.linalg.norm(ref["pe"])
+        assert e <= TOL, (label, inst.name, "P_e", e)
+        worst = max(worst, e)
+    return worst
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    cases = batch_cases()
+    return cases, [_oracle(inst) for inst in cases]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_vs_oracle(oracle_runs, use_graph):
+    cases, refs = oracle_runs
+    _say(f"[batch] {len(cases)} instances, graph={use_graph}")
+    bat = fdtd.Batch(cases, fdtd.batch_opts(use_graph=use_graph)).set_boundary().march()
+    _say(f"[batch] launches {bat.info()}")
+    for i, inst in enumerate(cases):
+        w = _compare_instance(bat, i, inst, refs[i], f"graph={use_graph}")
+        _say(f"[batch] {inst.name}: worst {w:.2e}")
+    bat.close()
+
+
+def test_graph_replays_match_plain_launches():
+    """the captured graph, replayed several times with other device work and
+    synchronisations in between, gives bitwise the plain launches' result"""
+    import torch
+    cases = batch_cases()
+    plain = fdtd.Batch(cases, fdtd.batch_opts(use_graph=False)).set_boundary().march()
+    want = [(plain.pe(i), plain.row_values(i, cases[i].Nt)) for i in range(len(cases))]
+    plain.close()
+    g = fdtd.Batch(cases, fdtd.batch_opts(use_graph=True))
+    x = torch.ones(1 << 20, dtype=torch.float64, device="cuda:0")
+    for rep in range(3):
+        _say(f"[batch] graph replay {rep}")
+        g.set_boundary().march()
+        x = x * 1.0001 + 1.0            # unrelated eager work on the same device
+        torch.cuda.synchronize()
+        for i in range(len(cases)):
+            assert np.array_equal(g.pe(i), want[i][0]), (rep, i)
+            assert np.array_equal(g.row_values(i, cases[i].Nt), want[i][1]), (rep, i)
+    g.close()
+
+
+def test_batch_matches_single_instance_march():
+    """the batch's wider workgroups change only the truncation of the
+    within-row recurrence, far below the parity bar"""
+    cases = batch_cases()[:3]
+    bat = fdtd.Batch(cases).set_boundary().march()
+    for i, inst in enumerate(cases):
+        one = fdtd.Solver(inst).set_boundary().march(inst.Nt)
+        a, b = bat.row_values(i, inst.Nt), one.row_values(inst.Nt)
+        assert np.linalg.norm(a - b) <= 1e-13 * max(np.linalg.norm(b), 1e-300), inst.name
+        assert np.linalg.norm(bat.pe(i) - one.pe()) <= 1e-13 * np.linalg.norm(one.pe())
+        one.close()
+    bat.close()
+
+
+def test_autotune_then_parity(oracle_runs):
+    cases, refs = oracle_runs
+    best, rate = fdtd.autotune(cases, probe_rows=64)
+    _say(f"[batch] autotune: tmax={best.tmax} wmax={best.wmax} graph={best.use_graph} rate={rate:.3g}")
+    assert best.use_graph == 1 and best.tmax in (8, 16, 32) and best.wmax in (768, 1536) and rate > 0
+    bat = fdtd.Batch(cases, best).set_boundary().march()
+    for i, inst in enumerate(cases):
+        _compare_instance(bat, i, inst, refs[i], "autotuned")
+    bat.close()
+
+
+def test_batch_state_errors():
+    cases = batch_cases()[:2]
+    bat = fdtd.Batch(cases)
+    with pytest.raises(fdtd.FdtdError) as e:
+        bat.march()                            # before the boundary
+    assert e.value.code == -3
+    bat.set_boundary().march()
+    with pytest.raises(fdtd.FdtdError) as e:
+        bat.march()                            # twice without a new boundary
+    assert e.value.code == -3
+    with pytest.raises(fdtd.FdtdError) as e:
+        bat.pe(5)                              # no such instance
+    assert e.value.code == -1
+    bat.close()
