@@ -34,7 +34,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--workload", choices=["large", "small", "batch"], default="large")
+    ap.add_argument("--batch", type=int, default=512, help="instances of the batched sweep")
+    ap.add_argument("--batch-seed", type=int, default=7)
+    ap.add_argument("--no-batch", action="store_true", help="leave the batched sweep out of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=600, help="rows past D in the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -105,6 +108,71 @@ def cpu_baseline(inst, extra_rows: int) -> dict:
                       f"({cells:.3g} cells, {t2 - t1:.1f} s; boundary table {t1 - t0:.1f} s not counted)"}
 
 
+def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
+    """The batched sweep: n seed-drawn heterogeneous instances (Gamma 2a in
+    [0.1, 10], k0 a in [0, 2 pi), width log-uniform in [0.2, 5], Delta in
+    {0.01, 0.005, 0.002}, Nx 1024..16384, Nt = 4 Nx) marched together.  One
+    step = boundary tables of every instance, the march of every row of every
+    instance (graph replay), and P_e of every instance into device memory."""
+    import torch
+
+    from paper_1707_05943_amd import fdtd
+    from paper_1707_05943_amd import workloads as W
+
+    insts = W.sweep_draw(n, seed)
+    dev = torch.device("cuda:0")
+    need = max(fdtd.batch_workspace_size(insts, fdtd.batch_opts(t, w)) for t in (32, 16, 8) for w in (0, 768))
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    t0 = time.perf_counter()
+    best, rate = fdtd.autotune(insts, probe_rows=256, workspace=ws)
+    t_tune = time.perf_counter() - t0
+    print(f"[bench] batch autotune: tmax={best.tmax} wmax={best.wmax} probe rate {rate:.3g} cells/s "
+          f"({t_tune:.1f} s)", file=sys.stderr, flush=True)
+    bat = fdtd.Batch(insts, best, workspace=ws)
+    stream = torch.cuda.current_stream(dev)
+    pe_dev = [torch.empty(i.Nt + 1, dtype=torch.float64, device=dev) for i in insts]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step(record=False):
+        if record:
+            ev[0].record(stream)
+        bat.set_boundary()
+        if record:
+            ev[1].record(stream)
+        bat.march()
+        if record:
+            ev[2].record(stream)
+        for i, inst in enumerate(insts):
+            bat.readout_device(i, fdtd.RO_PE, 0, pe_dev[i], inst.Nt + 1)
+        if record:
+            ev[3].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    tb = tm = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(record=True)
+        torch.cuda.synchronize()
+        tb += ev[0].elapsed_time(ev[1])
+        tm += ev[1].elapsed_time(ev[2])
+    t1 = time.perf_counter()
+    cells = float(sum(i.Nx * i.Nt for i in insts))
+    sec = (t1 - t0) / steps
+    info = bat.info()
+    bat.close()
+    del ws
+    torch.cuda.empty_cache()
+    return {"instances": n, "seed": seed, "cells": cells, "s_per_step": sec, "cell_updates_per_s": cells / sec,
+            "instances_per_s": n / sec, "march_ms": tm / steps, "boundary_ms": tb / steps,
+            "march_cell_updates_per_s": cells / (tm / steps * 1e-3), "launches": info["launches"],
+            "max_workgroups_per_launch": info["max_workgroups"],
+            "autotune": {"tmax": best.tmax, "wmax": best.wmax, "graph": bool(best.use_graph),
+                         "probe_rate": rate, "seconds": t_tune},
+            "ring_GB": sum((i.D + 2 * best.tmax + 2) * (i.Nx + 1) * 16 for i in insts) / 1e9}
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -119,6 +187,16 @@ def main():
 
     from paper_1707_05943_amd import fdtd
     from paper_1707_05943_amd import workloads as W
+
+    if args.workload == "batch":
+        b = run_batch(args.batch, args.batch_seed, args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": b["cell_updates_per_s"], "unit": "cell-updates/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": b["s_per_step"] * 1e3, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": f"batched sweep of {args.batch} instances"}, "batch": b}),
+              flush=True)
+        return
 
     inst = W.large_gauss() if args.workload == "large" else W.small_gauss()
     dev = torch.device("cuda:0")

@@ -62,6 +62,22 @@ enum fdtd_incident {
     FDTD_INC_GAUSS2 = 4  /* two identical Gaussian photons, phi ~ exp(-(x-x0)^2/(4 w^2) + i k (x-x0)) for x <= -a */
 };
 
+/* How fdtd_set_boundary computes E(t_r).  Both give E to FP64 rounding.
+ * FDTD_E_SERIES: the delay series of Eqs. (6), (9), (13), term by term with
+ *   gamma(n+1, z) (App. C); the Gaussian as a superposition of plane-wave
+ *   series over its Fourier components.  Work grows as Nt^2 / D per node.
+ * FDTD_E_DELAY_ODE: the generating sum G(t) = sum_m (G/2)^m J_m(t - 2ma) of
+ *   that series obeys G' = -W G + (Gamma/2) G(t - 2a) + phi(-a - t) exactly,
+ *   and E = sqrt(Gamma/2) [G(t) - G(t - 2a)] (for stimulated emission E = G
+ *   with G(0) = 1 and no drive).  The library integrates it step by step,
+ *   exactly for a forcing that is a polynomial of degree 15 on each step
+ *   (16 Gauss-Legendre collocation nodes, exponential weights), so the work is
+ *   linear in Nt.  Meant for long windows and small D (parameter sweeps). */
+enum fdtd_boundary_method {
+    FDTD_E_SERIES = 0,
+    FDTD_E_DELAY_ODE = 1
+};
+
 typedef struct fdtd_params {
     uint32_t abi_version;   /* FDTD_ABI_VERSION */
     uint32_t struct_size;   /* sizeof(fdtd_params) */
@@ -72,7 +88,7 @@ typedef struct fdtd_params {
     double omega0;          /* emitter frequency */
     double Gamma;           /* emitter decay rate */
     int32_t incident;       /* enum fdtd_incident */
-    int32_t reserved0;      /* must be 0 */
+    int32_t boundary;       /* enum fdtd_boundary_method: how E(t_r) is computed */
     double k;               /* carrier wavenumber of the incident packet */
     double alpha;           /* exponential packet width, units of Gamma (Eq. 7) */
     double x0;              /* Gaussian centre (x0 <= -a) */

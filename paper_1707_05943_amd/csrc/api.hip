@@ -64,6 +64,10 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
         snprintf(why, n, "Delta and Gamma must be > 0 and every parameter finite");
         return FDTD_EINVAL;
     }
+    if (p->boundary != FDTD_E_SERIES && p->boundary != FDTD_E_DELAY_ODE) {
+        snprintf(why, n, "unknown boundary method %d", p->boundary);
+        return FDTD_EINVAL;
+    }
     if (p->incident < FDTD_INC_PLANE || p->incident > FDTD_INC_GAUSS2) {
         snprintf(why, n, "unknown incident family %d", p->incident);
         return FDTD_EINVAL;
@@ -90,7 +94,7 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
 static int validate(const fdtd_params* p, char* why, size_t n) { return ctx_validate(p, SOLO_KNOBS, why, n); }
 
 struct Layout {
-    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, total;
+    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, total;
 };
 
 // ring rows: the delay reaches D+1 rows back; the strip runs one block of T
@@ -114,8 +118,60 @@ static Layout layout(const fdtd_params* p, const Plan& P)
     L.chi = off; off += align256(C * 16);
     L.Ebuf = off; off += align256(n * 16);
     L.status = off; off += 256;
+    L.Gn = off; off += align256((p->D + 1) * ODE_P * 16);
+    L.ode = off; off += align256((int64_t)sizeof(OdeTab));
+    L.odeinst = off; off += align256((int64_t)sizeof(OdeInst));
     L.total = off;
     return L;
+}
+
+// Gauss-Legendre rule on [-1, 1] (Newton on the Legendre recurrence)
+static void gl_rule(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// collocation weights of one step of the delay equation (OdeTab)
+static void ode_table(const Geom& g, OdeTab* T)
+{
+    double x[ODE_P], w[ODE_P];
+    gl_rule(ODE_P, x, w);
+    for (int i = 0; i < ODE_P; ++i) T->tau[i] = 0.5 * g.Delta * (1.0 + x[i]);
+    T->tau[ODE_P] = g.Delta;
+    enum { NQ = 48 };
+    double xq[NQ], wq[NQ];
+    gl_rule(NQ, xq, wq);
+    for (int i = 0; i <= ODE_P; ++i) {
+        const double ti = T->tau[i];
+        T->ew[i] = cexp_(-(g.W * ti));
+        for (int j = 0; j < ODE_P; ++j) {
+            cd acc = mk(0.0, 0.0);
+            for (int q = 0; q < NQ; ++q) {
+                const double u = 0.5 * ti * (1.0 + xq[q]);
+                double lj = 1.0;
+                for (int k = 0; k < ODE_P; ++k)
+                    if (k != j) lj *= (u - T->tau[k]) / (T->tau[j] - T->tau[k]);
+                acc += (0.5 * ti * wq[q] * lj) * cexp_(-(g.W * (ti - u)));
+            }
+            T->M[i][j] = acc;
+        }
+    }
 }
 
 static int plan_for(const fdtd_params* p, const PlanKnobs& kn, Plan* P, char* why, size_t n)
@@ -187,6 +243,9 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     b.chi = (cd*)(base + L.chi);
     b.Ebuf = (cd*)(base + L.Ebuf);
     b.status = (int*)(base + L.status);
+    b.Gn = (cd*)(base + L.Gn);
+    b.ode = (OdeTab*)(base + L.ode);
+    c->d_ode = (OdeInst*)(base + L.odeinst);
     c->row = -1;
     c->strip_row = -1;
     c->boundary_ready = 0;
@@ -195,6 +254,22 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
         free(c);
         snprintf(why, nwhy, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError()));
         return rc;
+    }
+    // the delay-equation boundary's step weights and launch record
+    OdeTab tab;
+    ode_table(g, &tab);
+    OdeInst oi;
+    memset(&oi, 0, sizeof oi);
+    oi.g = g;
+    oi.pk = pk;
+    oi.b = b;
+    hipError_t e = hipMemcpyAsync(b.ode, &tab, sizeof tab, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_ode, &oi, sizeof oi, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        free(c);
+        snprintf(why, nwhy, "copy of the boundary tables failed: %s", hipGetErrorString(e));
+        return FDTD_EDEVICE;
     }
     *out = c;
     return FDTD_OK;

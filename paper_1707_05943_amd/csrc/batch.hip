@@ -21,6 +21,8 @@ struct fdtd_batch {
     std::vector<int> order;          // instance ids, most launches first
     std::vector<BInst> h_tab;        // device table contents (sorted order)
     BInst* d_tab = nullptr;          // in the workspace
+    OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
+    int n_ode = 0;
     std::vector<int> n_active;       // per launch k: instances still marching
     std::vector<int> nb;             // per launch k: workgroups launched (multiple of 8)
     int64_t Lmax = 0;
@@ -84,7 +86,7 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
                        size_t nwhy)
 {
     const PlanKnobs kn = knobs_of(o);
-    int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst));
+    int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst)) + al256((int64_t)n * (int64_t)sizeof(OdeInst));
     for (int i = 0; i < n; ++i) {
         int rc = ctx_validate(&p[i], kn, why, nwhy);
         if (rc) {
@@ -161,6 +163,8 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     char* base = (char*)d_workspace;
     b->d_tab = (BInst*)base;
     int64_t off = al256((int64_t)n * (int64_t)sizeof(BInst));
+    b->d_ode = (OdeInst*)(base + off);
+    off += al256((int64_t)n * (int64_t)sizeof(OdeInst));
     for (int i = 0; i < n; ++i) {
         const int64_t sz = ctx_bytes(&p[i], kn);
         fdtd_ctx* c = nullptr;
@@ -212,6 +216,13 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     }
     hipError_t e = hipMemcpyAsync(b->d_tab, b->h_tab.data(), (size_t)n * sizeof(BInst), hipMemcpyHostToDevice,
                                   b->stream);
+    // delay-equation boundaries: one workgroup each in one launch, longest first
+    for (int q2 = 0; q2 < n && e == hipSuccess; ++q2) {
+        fdtd_ctx* c = b->c[b->order[q2]];
+        if (c->p.boundary != FDTD_E_DELAY_ODE) continue;
+        e = hipMemcpyAsync(b->d_ode + b->n_ode, c->d_ode, sizeof(OdeInst), hipMemcpyDeviceToDevice, b->stream);
+        ++b->n_ode;
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         destroy(b);
@@ -226,8 +237,24 @@ int fdtd_batch_set_boundary(fdtd_batch* b)
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     b->state = 0;
     for (int i = 0; i < b->n; ++i) {
-        int rc = ctx_boundary_enqueue(b->c[i]);
-        if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(b->c[i]));
+        fdtd_ctx* c = b->c[i];
+        if (c->p.boundary == FDTD_E_DELAY_ODE) {
+            c->boundary_ready = 0;
+            if (launch_boundary_pre(c)) return bfail(b, FDTD_EDEVICE, "instance %d: boundary launch failed", i);
+        } else {
+            int rc = ctx_boundary_enqueue(c);
+            if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(c));
+        }
+    }
+    if (b->n_ode) {
+        if (launch_E_ode(b->d_ode, b->n_ode, b->stream))
+            return bfail(b, FDTD_EDEVICE, "delay-equation boundary launch failed");
+        for (int i = 0; i < b->n; ++i) {
+            fdtd_ctx* c = b->c[i];
+            if (c->p.boundary != FDTD_E_DELAY_ODE) continue;
+            if (launch_E_from_G(c) || launch_boundary_post(c))
+                return bfail(b, FDTD_EDEVICE, "instance %d: boundary launch failed", i);
+        }
     }
     std::vector<int> st(b->n, 0);
     for (int i = 0; i < b->n; ++i) {

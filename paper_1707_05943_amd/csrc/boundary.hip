@@ -35,11 +35,15 @@
 
 namespace {
 
-__device__ inline cd gamma_star(int n, cd z, int* range_flag)
+// e^L gamma*(n, z): the scale factor enters the exponent, so that products
+// like T^m gamma*(m+1, bT) that are moderate while their factors are not stay
+// representable
+__device__ inline cd gamma_star_x(int n, cd z, cd L, int* range_flag)
 {
-    double az = cabs_(z);
+    const double az = cabs_(z);
     if (az <= (double)n + 0.5) {
-        cd term = mk(exp(-lgamma((double)n + 1.0)), 0.0);
+        // e^{-z}/n! sum_k z^k n!/(n+k)!
+        cd term = mk(1.0, 0.0);
         cd sum = term;
         for (int k = 1; k < 20000; ++k) {
             term = term * z * (1.0 / (double)(n + k));
@@ -47,19 +51,17 @@ __device__ inline cd gamma_star(int n, cd z, int* range_flag)
             if (norm2(term) <= 1e-36 * norm2(sum)) break;
             if (k == 19999) *range_flag = 1;
         }
-        return cexp_(-z) * sum;
+        return cexp_(L - z - mk(lgamma((double)n + 1.0), 0.0)) * sum;
     }
-    // inner = sum_{i=0}^{n-1} (n-1)!/(n-1-i)! z^{-i}
-    cd zi = cdiv(mk(1.0, 0.0), z);
+    // z^{-n} - e^{-z} z^{-1}/(n-1)! sum_{i=0}^{n-1} (n-1)!/(n-1-i)! z^{-i}
+    const cd zi = cdiv(mk(1.0, 0.0), z);
     cd t = mk(1.0, 0.0), s = mk(1.0, 0.0);
     for (int i = 0; i < n - 1; ++i) {
         t = t * zi * (double)(n - 1 - i);
         s += t;
     }
-    cd lz = clog_(z);
-    cd zn = cexp_(-(double)n * lz);
-    cd tail = cexp_(-z - lz - mk(lgamma((double)n), 0.0)) * s;
-    return zn - tail;
+    const cd lz = clog_(z);
+    return cexp_(L - (double)n * lz) - cexp_(L - z - lz - mk(lgamma((double)n), 0.0)) * s;
 }
 
 // sum over round trips for phi(-a-s) = e^{-lambda s} (the factor A e^{-ika}
@@ -74,17 +76,15 @@ __device__ cd delay_series(const Geom& g, cd lam, int64_t r, int* range_flag)
     for (int64_t m = 0; m * g.D < r; ++m) {
         const int64_t q = r - m * g.D;
         const double T = (double)q * g.Delta;
+        const double lT = log(T);
         const cd z = b * T;
-        const cd eL = cexp_(-(lam * T));
+        const cd mlT = -(lam * T);
         if (m == 0) {
-            sum += eL * (T * gamma_star(1, z, range_flag));
+            sum += gamma_star_x(1, z, mlT + mk(lT, 0.0), range_flag);          // e^{-lam T} T gamma*(1, z)
         } else {
-            const double lp = (double)(m - 1) * lhg + (double)m * log(T);
-            if (lp > 650.0) *range_flag = 1;
-            const double f1 = exp(lp) * T;
-            const double f2 = exp(lp - lgamma((double)m + 1.0));
-            sum += eL * (gmb * (f1 * gamma_star((int)m + 1, z, range_flag)));
-            sum -= f2 * cexp_(-(g.W * T));
+            const double lp = (double)(m - 1) * lhg + (double)m * lT;         // log (G/2)^{m-1} T^m
+            sum += gmb * gamma_star_x((int)m + 1, z, mlT + mk(lp + lT, 0.0), range_flag);
+            sum -= cexp_(mk(lp - lgamma((double)m + 1.0), 0.0) - g.W * T);
         }
     }
     return sqrt(hg) * sum;
@@ -163,15 +163,24 @@ __global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
     if (q < nblk) b.Ppart[q] = 0.0;
 }
 
-__global__ void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
+// source of E in k_E: computed here, copied from Ebuf, or formed from the
+// delay equation's G in Ebuf
+enum { E_COMPUTE = 0, E_COPY = 1, E_FROM_G = 2 };
+
+__global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
                     int nk, double k_lo, double hk)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > g.Nt) return;
     int range_flag = 0;
     cd E;
-    if (from_host) {
+    if (from_host == E_COPY) {
         E = b.Ebuf[r];
+    } else if (from_host == E_FROM_G) {
+        // E = sqrt(Gamma/2) [G(t) - G(t - 2a)]
+        E = b.Ebuf[r];
+        if (r >= g.D) E -= b.Ebuf[r - g.D];
+        E = sqrt(0.5 * g.Gamma) * E;
     } else if (pk.incident == FDTD_INC_EXP1) {
         E = stimulated(g, r);
     } else if (pk.incident == FDTD_INC_GAUSS2) {
@@ -216,6 +225,57 @@ __global__ void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
     (void)nblk;
 }
 
+// The delay equation G' = -W G + (Gamma/2) G(t - 2a) + phi(-a - t), G = 0
+// for t <= 0 (stimulated emission: no phi, G(0) = 1), stepped over t_rho =
+// rho Delta with the collocation weights of OdeTab.  One workgroup of one
+// wave per instance; lane i < ODE_P owns node i of every step and keeps that
+// node's values of the last D+1 steps in Gn (it reads back only what it wrote
+// itself), every lane carries G(t_rho).  G(t_r) goes to Ebuf[r].
+__global__ __launch_bounds__(64) void k_E_ode(const OdeInst* __restrict__ tab)
+{
+    const OdeInst& e = tab[blockIdx.x];
+    const Geom& g = e.g;
+    const Packet& pk = e.pk;
+    const Bufs& b = e.b;
+    const OdeTab* T = b.ode;
+    __shared__ cd f[2][ODE_P];
+    const int l = threadIdx.x;
+    const int64_t D = g.D, Nt = g.Nt, R = D + 1;
+    const double hg = 0.5 * g.Gamma;
+    const int stim = pk.incident == FDTD_INC_EXP1;
+    const int li = l < ODE_P ? l : 0;
+    cd Mi[ODE_P], Me[ODE_P];
+    #pragma unroll
+    for (int j = 0; j < ODE_P; ++j) {
+        Mi[j] = T->M[li][j];
+        Me[j] = T->M[ODE_P][j];
+    }
+    const cd ewi = T->ew[li], ewe = T->ew[ODE_P];
+    const double tau = T->tau[li];
+    cd G = stim ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    if (l == 0) b.Ebuf[0] = G;
+    for (int64_t rho = 0; rho < Nt; ++rho) {
+        const int par = (int)(rho & 1);
+        if (l < ODE_P) {
+            cd fo = mk(0.0, 0.0);
+            if (rho >= D) fo = hg * b.Gn[((rho - D) % R) * ODE_P + l];
+            if (!stim) fo += phi_in(pk, -g.a - (double)rho * g.Delta - tau);
+            f[par][l] = fo;
+        }
+        __syncthreads();
+        cd ai = ewi * G, ae = ewe * G;
+        #pragma unroll
+        for (int j = 0; j < ODE_P; ++j) {
+            const cd fj = f[par][j];
+            ai += Mi[j] * fj;
+            ae += Me[j] * fj;
+        }
+        if (l < ODE_P) b.Gn[(rho % R) * ODE_P + l] = ai;
+        G = ae;
+        if (l == 0) b.Ebuf[rho + 1] = G;
+    }
+}
+
 __global__ void k_clear_status(int* st)
 {
     if (threadIdx.x == 0) *st = 0;
@@ -255,23 +315,61 @@ static void gauss_nodes(const fdtd_ctx* c, int* nk, double* k_lo, double* hk)
     *hk = h;
 }
 
-int launch_boundary(fdtd_ctx* c, int from_host_E)
+int launch_boundary_pre(fdtd_ctx* c)
 {
     const int64_t n = c->g.Nt + 1;
     const int th = 128;
     const int64_t blocks = (n + th - 1) / th;
     hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, c->stream, c->b.status);
     hipLaunchKernelGGL(k_tables, dim3((unsigned)blocks), dim3(th), 0, c->stream, c->g, c->pk, c->b, c->nblk);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_boundary_E(fdtd_ctx* c, int mode)
+{
+    const int64_t n = c->g.Nt + 1;
     int nk = 0;
     double k_lo = 0.0, hk = 0.0;
-    if (c->p.incident == FDTD_INC_GAUSS2) gauss_nodes(c, &nk, &k_lo, &hk);
+    if (mode == E_COMPUTE && c->p.incident == FDTD_INC_GAUSS2) gauss_nodes(c, &nk, &k_lo, &hk);
     // small E-threads blocks: the work per row grows with r, so spread rows
     hipLaunchKernelGGL(k_E, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, c->stream, c->g, c->pk, c->b,
-                       from_host_E, c->nblk, nk, k_lo, hk);
+                       mode, c->nblk, nk, k_lo, hk);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_E_from_G(fdtd_ctx* c)
+{
+    return launch_boundary_E(c, c->p.incident == FDTD_INC_EXP1 ? E_COPY : E_FROM_G);
+}
+
+int launch_boundary_post(fdtd_ctx* c)
+{
     // row 0 of the ring is the initial condition (zero for x > -a)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, c->g.C);
     hipLaunchKernelGGL(k_md_row0, dim3((unsigned)((c->g.D + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_E_ode(const OdeInst* d_tab, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(64), 0, s, d_tab);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_boundary(fdtd_ctx* c, int from_host_E)
+{
+    int rc = launch_boundary_pre(c);
+    if (rc) return rc;
+    if (from_host_E) {
+        rc = launch_boundary_E(c, E_COPY);
+    } else if (c->p.boundary == FDTD_E_DELAY_ODE) {
+        rc = launch_E_ode(c->d_ode, 1, c->stream);
+        if (!rc) rc = launch_E_from_G(c);
+    } else {
+        rc = launch_boundary_E(c, E_COMPUTE);
+    }
+    if (rc) return rc;
+    return launch_boundary_post(c);
 }
 
 int launch_clear(fdtd_ctx* c)

@@ -68,6 +68,20 @@ struct Packet {           // incident packet phi and the exact-solution prefacto
     cd c_drive;           // drive = c_drive phi(xi) [phi(-a - t_c) - phi(a - t_c)]
 };
 
+// Delay-equation boundary (FDTD_E_DELAY_ODE): per step of width Delta, the
+// values of G at ODE_P Gauss-Legendre nodes tau_i in (0, Delta) and at tau_P =
+// Delta are  G(t + tau_i) = ew[i] G(t) + sum_j M[i][j] f(t + tau_j), with
+// ew[i] = e^{-W tau_i} and M[i][j] = int_0^{tau_i} e^{-W(tau_i - u)} l_j(u) du
+// (l_j the Lagrange basis on the nodes): exact when the forcing
+// f = (Gamma/2) G(. - 2a) + phi(-a - .) is a polynomial of degree < ODE_P on
+// the step.
+constexpr int ODE_P = 16;
+struct OdeTab {
+    double tau[ODE_P + 1];
+    cd ew[ODE_P + 1];
+    cd M[ODE_P + 1][ODE_P];
+};
+
 // device pointers carved from the caller's workspace
 struct Bufs {
     cd* ring;        // R x C
@@ -79,8 +93,17 @@ struct Bufs {
     double* Ppart;   // per-row per-block partial sums of |psi|^2
     double* Pe;      // P_e per row
     cd* chi;         // chi readout scratch
-    cd* Ebuf;        // host-supplied E staging (Nt+1)
+    cd* Ebuf;        // host-supplied E staging (Nt+1); G(t_r) of the delay-equation boundary
     int* status;     // device error flags
+    cd* Gn;          // delay-equation boundary: G at the nodes of the last D+1 steps ((D+1) x ODE_P)
+    OdeTab* ode;     // its step weights
+};
+
+// one instance of a (batched) delay-equation boundary launch
+struct OdeInst {
+    Geom g;
+    Packet pk;
+    Bufs b;
 };
 
 // Work decomposition of the blocked march (fixed per context).
@@ -110,6 +133,7 @@ struct Plan {
 
 struct fdtd_ctx {
     fdtd_params p;
+    OdeInst* d_ode;       // this instance's delay-equation launch record (in the workspace)
     Geom g;
     Packet pk;
     Bufs b;
@@ -126,6 +150,12 @@ enum { STATUS_GAMMA_RANGE = 1, STATUS_NONFINITE = 2 };
 
 // launch helpers implemented in the .hip files
 int launch_boundary(fdtd_ctx* c, int from_host_E);
+// the pieces of launch_boundary, for batches: status and tables; E; the rest
+int launch_boundary_pre(fdtd_ctx* c);
+int launch_boundary_E(fdtd_ctx* c, int from_host_E);
+int launch_boundary_post(fdtd_ctx* c);
+int launch_E_ode(const OdeInst* d_tab, int n, hipStream_t s);
+int launch_E_from_G(fdtd_ctx* c);
 int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst);
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst);

@@ -663,7 +663,10 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
                 P.strip_w = D;
             } else if (can_cone) {
                 P.cone_mode = 1;
-                int64_t Gs = (D + wm - 1) / wm;
+                // the strip's first workgroup holds its columns in half its threads
+                const int64_t half = (int64_t)(BM_THREADS / 2) * BM_K;
+                const int64_t ws = wm < half ? wm : half;
+                int64_t Gs = (D + ws - 1) / ws;
                 if (Gs < 2) Gs = 2;
                 P.strip_w = (D + Gs - 1) / Gs;
                 P.Gs = (int)((D + P.strip_w - 1) / P.strip_w);

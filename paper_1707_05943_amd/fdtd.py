@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 FDTD_ABI_VERSION = 1
 INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
 RO_ROW, RO_PE, RO_CHI, RO_E = 1, 2, 3, 4
+E_SERIES, E_DELAY_ODE = 0, 1
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", -4: "FDTD_EDEVICE",
           -5: "FDTD_ERANGE"}
 
@@ -34,7 +35,7 @@ class FdtdParams(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("struct_size", ctypes.c_uint32),
                 ("Nx", ctypes.c_int64), ("D", ctypes.c_int64), ("Nt", ctypes.c_int64),
                 ("Delta", ctypes.c_double), ("omega0", ctypes.c_double), ("Gamma", ctypes.c_double),
-                ("incident", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("incident", ctypes.c_int32), ("boundary", ctypes.c_int32),
                 ("k", ctypes.c_double), ("alpha", ctypes.c_double), ("x0", ctypes.c_double),
                 ("width", ctypes.c_double), ("phase", ctypes.c_double)]
 
@@ -103,7 +104,7 @@ def params(inst) -> FdtdParams:
     return FdtdParams(abi_version=FDTD_ABI_VERSION, struct_size=ctypes.sizeof(FdtdParams),
                       Nx=int(d["Nx"]), D=int(d["D"]), Nt=int(d["Nt"]), Delta=float(d["Delta"]),
                       omega0=float(d["omega0"]), Gamma=float(d["Gamma"]), incident=int(d["incident"]),
-                      reserved0=0, k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
+                      boundary=int(d.get("boundary", 0)), k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
                       x0=float(d.get("x0", 0.0)), width=float(d.get("width", 1.0)),
                       phase=float(d.get("phase", 0.0)))
 

@@ -45,6 +45,7 @@ class Instance:
     width: float = 1.0      # Gaussian std of |phi|^2
     phase: float = 0.0      # global phase theta of the two-photon state
     seed: int = 0
+    boundary: int = 0       # how the library computes E(t_r): 0 delay series, 1 delay equation
     extra: dict = field(default_factory=dict)
 
     @property
@@ -131,5 +132,6 @@ def sweep_draw(n: int, seed: int) -> list[Instance]:
         k0 = k0a / a
         out.append(Instance(name=f"sweep{seed}_{i}", Nx=Nx, D=D, Nt=4 * Nx, Delta=Delta,
                             omega0=k0, Gamma=Gamma, incident=INC_GAUSS2, k=k0,
-                            x0=-a - 8.0 * width, width=width, phase=theta, seed=seed * 100003 + i))
+                            x0=-a - 8.0 * width, width=width, phase=theta, seed=seed * 100003 + i,
+                            boundary=1))
     return out

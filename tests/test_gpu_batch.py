@@ -29,8 +29,10 @@ def _gauss(D, Nx, Nt, Delta, width, seed, k0a=0.5 * math.pi, x0w=6.0):
 
 def batch_cases():
     """different D (and so different rows per block), widths, lengths and
-    families; the instances finish after different numbers of launches"""
-    return [
+    families; the instances finish after different numbers of launches; the
+    boundary of every other instance comes from the delay equation (one
+    batched launch for those), the rest from the delay series"""
+    cases = [
         _gauss(10, 2600, 300, 0.02, 0.5, 31),                 # T = 8, several workgroups
         _gauss(40, 1025, 200, 0.025, 0.6, 32),                # T = 32
         _gauss(2, 3, 50, 0.1, 0.4, 33),                       # Nx = D + 1, T = 2
@@ -41,6 +43,9 @@ def batch_cases():
         W.Instance(name="coarse_b", Nx=1500, D=24, Nt=300, Delta=0.5, omega0=4.5, Gamma=1.0,
                    incident=W.INC_GAUSS2, k=4.5, x0=-6.0 - 8 * 3.0, width=3.0, phase=0.3),
     ]
+    for i, c in enumerate(cases):
+        c.boundary = i % 2
+    return cases
 
 
 def _oracle(inst):

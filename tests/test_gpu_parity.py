@@ -5,6 +5,8 @@ the chi readout of Eq. 2, the boundary table E(t_r)).  The march is checked
 both with the oracle's own E table handed to the library (isolating the
 march) and end to end (the library's gamma-function boundary kernel).
 """
+import copy
+import functools
 import math
 import sys
 
@@ -133,20 +135,49 @@ E_CASES = {
     "exp2_a16": _fam("exp2_a16", W.INC_EXP2, alpha=1.6, k=2.0),     # Re z < 0 on the real axis
     "exp2_a25": _fam("exp2_a25", W.INC_EXP2, alpha=2.5, k=2.4),     # Re z < 0 off the axis
     "exp1": _fam("exp1", W.INC_EXP1, alpha=0.5),
+    # 120 round trips in the window
+    "gauss_long_D10": _gauss(10, 64, 1200, 0.01, 0.3, 5, k0a=2.5),
 }
 
 
+@functools.lru_cache(maxsize=None)
+def _oracle_E(name):
+    return oracle.E_table(E_CASES[name])
+
+
+@pytest.mark.parametrize("method", [fdtd.E_SERIES, fdtd.E_DELAY_ODE])
 @pytest.mark.parametrize("name", list(E_CASES))
-def test_boundary_table(name):
-    inst = E_CASES[name]
-    _say(f"[parity] boundary E: {name} D={inst.D} Nt={inst.Nt}")
-    ref = oracle.E_table(inst)
+def test_boundary_table(name, method):
+    inst = copy.copy(E_CASES[name])
+    inst.boundary = method
+    _say(f"[parity] boundary E: {name} D={inst.D} Nt={inst.Nt} method={method}")
+    ref = _oracle_E(name)
     c = 1.0 if inst.incident == W.INC_EXP1 else math.sqrt(2.0) * np.exp(1j * inst.phase)
     sol = fdtd.Solver(inst).set_boundary()
     got = sol.E() / c
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     assert err <= TOL, err
     sol.close()
+
+
+def test_boundary_methods_agree_on_a_long_window():
+    """300 round trips over a window of 60/Gamma: the series method's factors
+    (G/2)^(m-1) T^m reach e^1000 there and only their products with
+    gamma*(m+1, bT) are representable; the delay-equation method steps
+    through the same window.  Two independent evaluations of E must agree."""
+    base = _gauss(10, 64, 3000, 0.02, 1.0, 6, k0a=1.2)
+    got = {}
+    for method in (fdtd.E_SERIES, fdtd.E_DELAY_ODE):
+        inst = copy.copy(base)
+        inst.boundary = method
+        _say(f"[parity] long window, method {method}")
+        sol = fdtd.Solver(inst).set_boundary()
+        got[method] = sol.E()
+        sol.close()
+    a, b = got[fdtd.E_SERIES], got[fdtd.E_DELAY_ODE]
+    err = np.max(np.abs(a - b)) / np.max(np.abs(b))
+    _say(f"[parity] long window: methods differ by {err:.2e}")
+    assert err <= TOL, err
 
 
 def test_small_gauss_end_to_end():
