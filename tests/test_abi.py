@@ -12,20 +12,34 @@ from paper_1707_05943_amd import workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+def _declared(header="fdtd.h", prefix="fdtd_"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(fdtd_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_binding_exports():
     assert _declared() == sorted(fdtd.EXPORTS)
+    from paper_1707_05943_amd import surrogate
+    assert _declared("surrogate.h", "sur_") == sorted(surrogate.EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     lib = fdtd.load()
-    for name in _declared():
+    for name in _declared() + _declared("surrogate.h", "sur_"):
         assert hasattr(lib, name), name
+
+
+def test_surrogate_sizes_on_the_host():
+    from paper_1707_05943_amd import surrogate
+    n, ws = surrogate.sizes(surrogate.cfg())
+    # lift 7x64+64, 4 layers of 2 x 64 modes x 64 x 64 + 64 x 64 + 64, projection 64x128+128, 128x3+3
+    assert n == 7 * 64 + 64 + 4 * (2 * 64 * 64 * 64 + 64 * 64 + 64) + 64 * 128 + 128 + 128 * 3 + 3
+    assert ws > 0
+    bad = surrogate.cfg(modes=600)
+    with pytest.raises(surrogate.SurError) as e:
+        surrogate.sizes(bad)
+    assert e.value.code == -1
 
 
 def test_params_struct_layout_matches_header():
