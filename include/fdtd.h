@@ -205,6 +205,20 @@ int fdtd_batch_march(fdtd_batch *b);
 int fdtd_batch_readout(fdtd_batch *b, int32_t i, int32_t what, int64_t arg, void *dst, int64_t count,
                        int32_t dst_on_device);
 
+/* chi snapshots taken during the next marches: for instance i with
+ * rows[i] >= 0, chi of Eq. (2) at row rows[i], detectors x1 = a + Delta and
+ * x2 = x1 + k strides[i] Delta for k < n_tau (zero where x2 is beyond the
+ * last column), into d_out[i n_tau + k] (device, complex doubles).  rows[i] < 0
+ * takes none for that instance; rows = NULL switches snapshots off.  The
+ * snapshot is taken right after the launch that completes its row, while the
+ * ring still holds every row Eq. (2) reads.  Re-captures the graph. */
+int fdtd_batch_set_chi(fdtd_batch *b, const int64_t *rows, const int64_t *strides, int64_t n_tau, void *d_out);
+
+/* P_e(t_k) of every instance after a march at t_k = k Nt Delta / (n_samples - 1),
+ * linear between rows, into d_out[i n_samples + k] (device doubles, the
+ * caller's instance order); enqueued on the batch's stream. */
+int fdtd_batch_sample_pe(fdtd_batch *b, int64_t n_samples, double *d_out);
+
 /* Launches of one march, and workgroups of the first (largest) launch. */
 int fdtd_batch_info(const fdtd_batch *b, int64_t *launches, int64_t *max_workgroups);
 

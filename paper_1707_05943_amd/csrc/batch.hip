@@ -23,6 +23,9 @@ struct fdtd_batch {
     BInst* d_tab = nullptr;          // in the workspace
     OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
     int n_ode = 0;
+    ChiJob* d_jobs = nullptr;        // chi snapshots, sorted by the launch after which they are taken
+    std::vector<int> job_begin;      // per launch k: first job, and one past the last (job_begin[k+1])
+    int64_t chi_ntau = 0;
     std::vector<int> n_active;       // per launch k: instances still marching
     std::vector<int> nb;             // per launch k: workgroups launched (multiple of 8)
     int64_t Lmax = 0;
@@ -86,7 +89,8 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
                        size_t nwhy)
 {
     const PlanKnobs kn = knobs_of(o);
-    int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst)) + al256((int64_t)n * (int64_t)sizeof(OdeInst));
+    int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst)) + al256((int64_t)n * (int64_t)sizeof(OdeInst)) +
+                al256((int64_t)n * (int64_t)sizeof(ChiJob));
     for (int i = 0; i < n; ++i) {
         int rc = ctx_validate(&p[i], kn, why, nwhy);
         if (rc) {
@@ -111,14 +115,28 @@ static void destroy(fdtd_batch* b)
     delete b;
 }
 
-// the launches of the batch from launch k0 to k1-1 on stream s
+// the launches of the batch from launch k0 to k1-1 on stream s, each
+// followed by the chi snapshots whose row it completes
 static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
 {
     for (int64_t k = k0; k < k1 && k < b->Lmax; ++k) {
         int rc = launch_block_batch(b->d_tab, b->n_active[k], k, b->nb[k], s);
         if (rc) return rc;
+        if (!b->job_begin.empty()) {
+            const int j0 = b->job_begin[k], j1 = b->job_begin[k + 1];
+            rc = launch_chi_batch(b->d_jobs + j0, j1 - j0, b->chi_ntau, s);
+            if (rc) return rc;
+        }
     }
     return FDTD_OK;
+}
+
+static void drop_graph(fdtd_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
 }
 
 extern "C" {
@@ -143,7 +161,7 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     char why[320];
     if (!out) return bfail(nullptr, FDTD_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!p || n < 1) return bfail(nullptr, FDTD_EINVAL, "params and n >= 1 are required");
+    if (!p || n < 1 || n > 65535) return bfail(nullptr, FDTD_EINVAL, "params and 1 <= n <= 65535 are required");
     fdtd_batch_opts o;
     int rc = opts_check(opts, &o, why, sizeof why);
     if (rc) return bfail(nullptr, rc, "%s", why);
@@ -165,6 +183,8 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     int64_t off = al256((int64_t)n * (int64_t)sizeof(BInst));
     b->d_ode = (OdeInst*)(base + off);
     off += al256((int64_t)n * (int64_t)sizeof(OdeInst));
+    b->d_jobs = (ChiJob*)(base + off);
+    off += al256((int64_t)n * (int64_t)sizeof(ChiJob));
     for (int i = 0; i < n; ++i) {
         const int64_t sz = ctx_bytes(&p[i], kn);
         fdtd_ctx* c = nullptr;
@@ -197,6 +217,7 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
         e.P = c->plan;
         e.wg_begin = wg;
         e.launches = L[b->order[q]];
+        e.index = b->order[q];
         wg += c->plan.nwg;
         wg_end[q] = wg;
         b->h_tab.push_back(e);
@@ -312,6 +333,62 @@ int fdtd_batch_readout(fdtd_batch* b, int32_t i, int32_t what, int64_t arg, void
     int rc = fdtd_readout(b->c[i], what, arg, dst, count, dst_on_device);
     if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(b->c[i]));
     return FDTD_OK;
+}
+
+int fdtd_batch_set_chi(fdtd_batch* b, const int64_t* rows, const int64_t* strides, int64_t n_tau, void* d_out)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    drop_graph(b);
+    b->job_begin.clear();
+    b->chi_ntau = 0;
+    if (!rows) return FDTD_OK;                        // snapshots off
+    if (!strides || n_tau < 1 || !d_out) return bfail(b, FDTD_EINVAL, "strides, n_tau >= 1 and d_out are required");
+    std::vector<ChiJob> jobs;
+    std::vector<int64_t> kstar;
+    for (int i = 0; i < b->n; ++i) {
+        const fdtd_ctx* c = b->c[i];
+        if (rows[i] < 0) continue;
+        if (rows[i] > c->p.Nt || strides[i] < 1)
+            return bfail(b, FDTD_EINVAL, "instance %d: snapshot row %lld outside 0..Nt or stride < 1", i,
+                         (long long)rows[i]);
+        ChiJob j;
+        memset(&j, 0, sizeof j);
+        j.g = c->g;
+        j.b = c->b;
+        j.c0 = chi0_coefficient(&c->p);
+        j.row = rows[i];
+        j.stride = strides[i];
+        j.n_tau = n_tau;
+        j.dst = (cd*)d_out + (int64_t)i * n_tau;
+        jobs.push_back(j);
+        // the first launch after which row `row` is complete in every column
+        kstar.push_back(rows[i] == 0 ? 0 : (rows[i] + c->plan.T - 1) / c->plan.T);
+    }
+    std::vector<int> idx(jobs.size());
+    for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int)q;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return kstar[x] < kstar[y]; });
+    std::vector<ChiJob> sorted;
+    for (int q : idx) sorted.push_back(jobs[q]);
+    b->job_begin.assign(b->Lmax + 1, 0);
+    for (int q : idx) b->job_begin[kstar[q] + 1]++;
+    for (int64_t k = 0; k < b->Lmax; ++k) b->job_begin[k + 1] += b->job_begin[k];
+    b->chi_ntau = n_tau;
+    if (!sorted.empty()) {
+        hipError_t e = hipMemcpyAsync(b->d_jobs, sorted.data(), sorted.size() * sizeof(ChiJob),
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "copy of the snapshot table failed: %s", hipGetErrorString(e));
+    }
+    return FDTD_OK;
+}
+
+int fdtd_batch_sample_pe(fdtd_batch* b, int64_t n_samples, double* d_out)
+{
+    if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
+    if (b->state != 2) return bfail(b, FDTD_ESTATE, "sample P_e after a march");
+    if (n_samples < 1 || !d_out) return bfail(b, FDTD_EINVAL, "n_samples >= 1 and d_out are required");
+    int rc = launch_pe_sample_batch(b->d_tab, b->n, n_samples, d_out, b->stream);
+    return rc ? bfail(b, rc, "launch failed") : FDTD_OK;
 }
 
 int fdtd_batch_info(const fdtd_batch* b, int64_t* launches, int64_t* max_workgroups)

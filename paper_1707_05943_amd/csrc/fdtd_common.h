@@ -209,9 +209,23 @@ struct BInst {
     Plan P;
     int64_t wg_begin;    // first workgroup of this instance in a launch
     int64_t launches;    // 1 + ceil(Nt / T)
+    int64_t index;       // the instance's position in the caller's order
 };
 
 int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipStream_t s);
+
+// A chi snapshot of one instance at row `row`, detector separations
+// k * stride * Delta for k < n_tau (zero beyond the last column).
+struct ChiJob {
+    Geom g;
+    Bufs b;
+    cd c0;               // coefficient of the free two-photon term of Eq. (2)
+    int64_t row, stride, n_tau;
+    cd* dst;
+};
+int launch_chi_batch(const ChiJob* d_jobs, int n, int64_t n_tau, hipStream_t s);
+int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t n_samples, double* dst, hipStream_t s);
+cd chi0_coefficient(const fdtd_params* p);
 
 // Internal context life cycle, shared by the one-instance and batched ABIs.
 int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn);

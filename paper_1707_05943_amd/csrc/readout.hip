@@ -30,17 +30,55 @@ __global__ void k_pe_final(Geom g, Bufs b, int64_t nrows, int64_t nblk, double* 
 // x2 = x1 + k Delta (column D+1+k):
 //   chi0(x1 - t, x2 - t) - (sqrt(G)/2) [psi(-k, r-D-1-k) - psi(D-k, r-1-k)
 //                                       + psi(k, r-D-1) - psi(D+k, r-1)]
-__global__ void k_chi(Geom g, Bufs b, cd c_chi0, int64_t r, int64_t count, cd* dst)
+__device__ cd chi_at(const Geom& g, const Bufs& b, cd c_chi0, int64_t r, int64_t k)
 {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= count) return;
     const int64_t D = g.D;
     cd c0 = mk(0.0, 0.0);
     const int64_t q1 = r - D - 1, q2 = r - D - 1 - k;
     if (q1 >= 0 && q2 >= 0) c0 = c_chi0 * (b.Phi[q1] * b.Phi[q2]);
     cd acc = psi_rd(g, b, -k, r - D - 1 - k) - psi_rd(g, b, D - k, r - 1 - k)
            + psi_rd(g, b, k, r - D - 1) - psi_rd(g, b, D + k, r - 1);
-    dst[k] = c0 - (0.5 * sqrt(g.Gamma)) * acc;
+    return c0 - (0.5 * sqrt(g.Gamma)) * acc;
+}
+
+__global__ void k_chi(Geom g, Bufs b, cd c_chi0, int64_t r, int64_t count, cd* dst)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    dst[k] = chi_at(g, b, c_chi0, r, k);
+}
+
+// snapshots of several instances (one per blockIdx.y)
+__global__ void k_chi_batch(const ChiJob* __restrict__ jobs)
+{
+    const ChiJob& j = jobs[blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= j.n_tau) return;
+    const int64_t kk = k * j.stride;
+    j.dst[k] = (kk < j.g.Nx - j.g.D) ? chi_at(j.g, j.b, j.c0, j.row, kk) : mk(0.0, 0.0);
+}
+
+// P_e(t) of several instances (one per blockIdx.y) at t_k = k T / (n - 1),
+// T = Nt Delta, linear in t between rows
+__global__ void k_pe_sample(const BInst* __restrict__ tab, int64_t ns, double* dst)
+{
+    const BInst& e = tab[blockIdx.y];
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ns) return;
+    const int64_t Nt = e.g.Nt, nw = e.P.nwg;
+    const double pos = ns > 1 ? (double)k * (double)Nt / (double)(ns - 1) : 0.0;
+    int64_t r0 = (int64_t)floor(pos);
+    if (r0 > Nt) r0 = Nt;
+    const int64_t r1 = r0 < Nt ? r0 + 1 : Nt;
+    const double f = pos - (double)r0;
+    double p[2];
+    const int64_t rr[2] = {r0, r1};
+    for (int q = 0; q < 2; ++q) {
+        double s = 0.0;
+        for (int64_t w = 0; w < nw; ++w) s += e.b.Ppart[rr[q] * nw + w];
+        p[q] = e.b.Pex[rr[q]] + e.g.Delta * s;
+    }
+    dst[e.index * ns + k] = (1.0 - f) * p[0] + f * p[1];
 }
 
 __global__ void k_row_copy(Geom g, Bufs b, int64_t rho, cd* dst)
@@ -59,9 +97,27 @@ int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst)
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
+cd chi0_coefficient(const fdtd_params* p)
+{
+    return (p->incident == FDTD_INC_EXP1) ? mk(0.0, 0.0) : mk(cos(p->phase), sin(p->phase));
+}
+
+int launch_chi_batch(const ChiJob* d_jobs, int n, int64_t n_tau, hipStream_t s)
+{
+    if (n <= 0) return FDTD_OK;
+    hipLaunchKernelGGL(k_chi_batch, dim3((unsigned)((n_tau + 255) / 256), (unsigned)n), dim3(256), 0, s, d_jobs);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t ns, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pe_sample, dim3((unsigned)((ns + 255) / 256), (unsigned)n), dim3(256), 0, s, d_tab, ns, dst);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst)
 {
-    cd c_chi0 = (c->p.incident == FDTD_INC_EXP1) ? mk(0.0, 0.0) : mk(cos(c->p.phase), sin(c->p.phase));
+    cd c_chi0 = chi0_coefficient(&c->p);
     hipLaunchKernelGGL(k_chi, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b, c_chi0,
                        r, count, dst);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;

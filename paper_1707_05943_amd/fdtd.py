@@ -28,7 +28,7 @@ EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_bo
            "fdtd_describe", "fdtd_strerror", "fdtd_last_error",
            "fdtd_batch_workspace_size", "fdtd_batch_init", "fdtd_batch_set_boundary", "fdtd_batch_march",
            "fdtd_batch_readout", "fdtd_batch_info", "fdtd_batch_sync", "fdtd_batch_destroy",
-           "fdtd_batch_last_error", "fdtd_batch_autotune")
+           "fdtd_batch_last_error", "fdtd_batch_autotune", "fdtd_batch_set_chi", "fdtd_batch_sample_pe")
 
 
 class FdtdParams(ctypes.Structure):
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.fdtd_batch_last_error.argtypes = [vp]
     lib.fdtd_batch_last_error.restype = ctypes.c_char_p
     lib.fdtd_batch_autotune.argtypes = [P, i32, vp, ctypes.c_size_t, vp, i64, BO, ctypes.POINTER(ctypes.c_double)]
+    lib.fdtd_batch_set_chi.argtypes = [vp, vp, vp, i64, vp]
+    lib.fdtd_batch_sample_pe.argtypes = [vp, i64, vp]
     _lib = lib
     return lib
 
@@ -281,6 +283,25 @@ class Batch:
     def march(self):
         self._check(self.lib.fdtd_batch_march(self.h))
         return self
+
+    def set_chi(self, rows, strides, n_tau: int, out):
+        """chi snapshots at rows[i] with detector stride strides[i] into the device
+        tensor `out` (complex128, n x n_tau); rows=None switches them off"""
+        if rows is None:
+            self._check(self.lib.fdtd_batch_set_chi(self.h, None, None, 0, None))
+            return self
+        self._rows = np.ascontiguousarray(rows, dtype=np.int64)
+        self._strides = np.ascontiguousarray(strides, dtype=np.int64)
+        self._check(self.lib.fdtd_batch_set_chi(self.h, self._rows.ctypes.data_as(ctypes.c_void_p),
+                                                self._strides.ctypes.data_as(ctypes.c_void_p), int(n_tau),
+                                                ctypes.c_void_p(out.data_ptr())))
+        return self
+
+    def sample_pe(self, n_samples: int, out):
+        """P_e at n_samples equally spaced times of each instance's window into the
+        device tensor `out` (float64, n x n_samples)"""
+        self._check(self.lib.fdtd_batch_sample_pe(self.h, int(n_samples), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def info(self) -> dict:
         a, b = ctypes.c_int64(0), ctypes.c_int64(0)

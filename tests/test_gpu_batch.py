@@ -160,3 +160,46 @@ def test_batch_state_errors():
         bat.pe(5)                              # no such instance
     assert e.value.code == -1
     bat.close()
+
+
+def test_chi_snapshots_and_pe_samples(oracle_runs):
+    """chi taken during the (graph-captured) batched march at a row of each
+    instance, with a detector stride, and P_e sampled on a fixed grid of each
+    instance's window, against the oracle"""
+    import torch
+    cases = batch_cases()
+    n_tau, ns = 40, 257
+    # at the peak of P_e, where the field is alive
+    rows = [max(1, int(np.argmax(oracle_runs[1][i]["pe"]))) for i in range(len(cases))]
+    rows[2] = -1                                             # no snapshot for this one
+    strides = [1 + (i % 3) for i in range(len(cases))]
+    out = torch.zeros(len(cases), n_tau, dtype=torch.complex128, device="cuda:0")
+    pes = torch.zeros(len(cases), ns, dtype=torch.float64, device="cuda:0")
+    bat = fdtd.Batch(cases, fdtd.batch_opts(use_graph=True))
+    bat.set_chi(rows, strides, n_tau, out)
+    for rep in range(2):                                     # the graph replays the snapshots too
+        bat.set_boundary().march()
+        bat.sample_pe(ns, pes)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        got_pe = pes.cpu().numpy()
+        for i, inst in enumerate(cases):
+            ref_pe = oracle_runs[1][i]["pe"]
+            pos = np.arange(ns) * inst.Nt / (ns - 1)
+            want_pe = np.interp(pos, np.arange(inst.Nt + 1), ref_pe)
+            if inst.incident != W.INC_PLANE:
+                e = np.linalg.norm(got_pe[i] - want_pe) / np.linalg.norm(want_pe)
+                assert e <= TOL, (rep, inst.name, "P_e samples", e)
+            if rows[i] < 0:
+                assert np.all(got[i] == 0)
+                continue
+            navail = min(n_tau * strides[i], inst.Nx - inst.D)
+            ref = oracle.march(inst, oracle.E_table(inst), chi_rows=[rows[i]], n_tau=navail, want_ring=False)
+            want = np.zeros(n_tau, dtype=complex)
+            sel = np.arange(n_tau) * strides[i]
+            ok = sel < navail
+            want[ok] = ref["chi"][0][sel[ok]]
+            e = np.linalg.norm(got[i] - want) / max(np.linalg.norm(want), 1e-300)
+            _say(f"[batch] chi snapshot {inst.name} row {rows[i]} stride {strides[i]}: {e:.2e}")
+            assert e <= TOL, (rep, inst.name, "chi", e)
+    bat.close()
