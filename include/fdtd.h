@@ -214,10 +214,12 @@ int fdtd_batch_readout(fdtd_batch *b, int32_t i, int32_t what, int64_t arg, void
  * ring still holds every row Eq. (2) reads.  Re-captures the graph. */
 int fdtd_batch_set_chi(fdtd_batch *b, const int64_t *rows, const int64_t *strides, int64_t n_tau, void *d_out);
 
-/* P_e(t_k) of every instance after a march at t_k = k Nt Delta / (n_samples - 1),
+/* P_e(t_k) of every instance after a march at t_k = k t_end[i] / (n_samples - 1),
  * linear between rows, into d_out[i n_samples + k] (device doubles, the
- * caller's instance order); enqueued on the batch's stream. */
-int fdtd_batch_sample_pe(fdtd_batch *b, int64_t n_samples, double *d_out);
+ * caller's instance order); enqueued on the batch's stream.  d_t_end is a
+ * device array of n window ends (at most Nt Delta; 0 or a NULL array means
+ * Nt Delta). */
+int fdtd_batch_sample_pe(fdtd_batch *b, int64_t n_samples, const double *d_t_end, double *d_out);
 
 /* Launches of one march, and workgroups of the first (largest) launch. */
 int fdtd_batch_info(const fdtd_batch *b, int64_t *launches, int64_t *max_workgroups);

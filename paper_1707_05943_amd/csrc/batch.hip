@@ -382,12 +382,12 @@ int fdtd_batch_set_chi(fdtd_batch* b, const int64_t* rows, const int64_t* stride
     return FDTD_OK;
 }
 
-int fdtd_batch_sample_pe(fdtd_batch* b, int64_t n_samples, double* d_out)
+int fdtd_batch_sample_pe(fdtd_batch* b, int64_t n_samples, const double* d_t_end, double* d_out)
 {
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     if (b->state != 2) return bfail(b, FDTD_ESTATE, "sample P_e after a march");
     if (n_samples < 1 || !d_out) return bfail(b, FDTD_EINVAL, "n_samples >= 1 and d_out are required");
-    int rc = launch_pe_sample_batch(b->d_tab, b->n, n_samples, d_out, b->stream);
+    int rc = launch_pe_sample_batch(b->d_tab, b->n, n_samples, d_t_end, d_out, b->stream);
     return rc ? bfail(b, rc, "launch failed") : FDTD_OK;
 }
 

@@ -224,7 +224,8 @@ struct ChiJob {
     cd* dst;
 };
 int launch_chi_batch(const ChiJob* d_jobs, int n, int64_t n_tau, hipStream_t s);
-int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t n_samples, double* dst, hipStream_t s);
+int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t n_samples, const double* d_tend, double* dst,
+                           hipStream_t s);
 cd chi0_coefficient(const fdtd_params* p);
 
 // Internal context life cycle, shared by the one-instance and batched ABIs.

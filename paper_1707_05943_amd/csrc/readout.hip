@@ -60,13 +60,16 @@ __global__ void k_chi_batch(const ChiJob* __restrict__ jobs)
 
 // P_e(t) of several instances (one per blockIdx.y) at t_k = k T / (n - 1),
 // T = Nt Delta, linear in t between rows
-__global__ void k_pe_sample(const BInst* __restrict__ tab, int64_t ns, double* dst)
+__global__ void k_pe_sample(const BInst* __restrict__ tab, int64_t ns, const double* __restrict__ t_end,
+                            double* dst)
 {
     const BInst& e = tab[blockIdx.y];
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ns) return;
     const int64_t Nt = e.g.Nt, nw = e.P.nwg;
-    const double pos = ns > 1 ? (double)k * (double)Nt / (double)(ns - 1) : 0.0;
+    // rows of t_k = k t_end / (ns - 1), t_end = Nt Delta unless given
+    const double rows_end = (t_end && t_end[e.index] > 0.0) ? t_end[e.index] / e.g.Delta : (double)Nt;
+    const double pos = ns > 1 ? (double)k * rows_end / (double)(ns - 1) : 0.0;
     int64_t r0 = (int64_t)floor(pos);
     if (r0 > Nt) r0 = Nt;
     const int64_t r1 = r0 < Nt ? r0 + 1 : Nt;
@@ -109,9 +112,10 @@ int launch_chi_batch(const ChiJob* d_jobs, int n, int64_t n_tau, hipStream_t s)
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
-int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t ns, double* dst, hipStream_t s)
+int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t ns, const double* d_tend, double* dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pe_sample, dim3((unsigned)((ns + 255) / 256), (unsigned)n), dim3(256), 0, s, d_tab, ns, dst);
+    hipLaunchKernelGGL(k_pe_sample, dim3((unsigned)((ns + 255) / 256), (unsigned)n), dim3(256), 0, s, d_tab, ns,
+                       d_tend, dst);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 

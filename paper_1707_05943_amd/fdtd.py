@@ -96,7 +96,7 @@ def load(path: str = LIB_PATH):
     lib.fdtd_batch_last_error.restype = ctypes.c_char_p
     lib.fdtd_batch_autotune.argtypes = [P, i32, vp, ctypes.c_size_t, vp, i64, BO, ctypes.POINTER(ctypes.c_double)]
     lib.fdtd_batch_set_chi.argtypes = [vp, vp, vp, i64, vp]
-    lib.fdtd_batch_sample_pe.argtypes = [vp, i64, vp]
+    lib.fdtd_batch_sample_pe.argtypes = [vp, i64, vp, vp]
     _lib = lib
     return lib
 
@@ -297,10 +297,12 @@ class Batch:
                                                 ctypes.c_void_p(out.data_ptr())))
         return self
 
-    def sample_pe(self, n_samples: int, out):
-        """P_e at n_samples equally spaced times of each instance's window into the
-        device tensor `out` (float64, n x n_samples)"""
-        self._check(self.lib.fdtd_batch_sample_pe(self.h, int(n_samples), ctypes.c_void_p(out.data_ptr())))
+    def sample_pe(self, n_samples: int, out, t_end=None):
+        """P_e at n_samples equally spaced times of each instance's window (or of
+        [0, t_end[i]], a float64 device tensor) into the device tensor `out`
+        (float64, n x n_samples)"""
+        te = ctypes.c_void_p(t_end.data_ptr()) if t_end is not None else None
+        self._check(self.lib.fdtd_batch_sample_pe(self.h, int(n_samples), te, ctypes.c_void_p(out.data_ptr())))
         return out
 
     def info(self) -> dict:
