@@ -44,24 +44,32 @@ struct GemmArgs {
     long long sA, sB, sC;     // batch strides (elements)
     int transA, transB;
     float alpha, beta;
+    int splits;               // split of K over blockIdx.z (1: none)
+    float* part;              // splits > 1: raw products, (batch, splits, M, N)
 };
 
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
 {
     __shared__ __bf16 As[GB_M][GB_LD];     // As[i][k]
     __shared__ __bf16 Bs[GB_N][GB_LD];     // Bs[j][k]
-    const int z = blockIdx.z;
+    const int z = blockIdx.z / a.splits, sp = blockIdx.z % a.splits;
     const float* A = a.A + z * a.sA;
     const float* B = a.B + z * a.sB;
     float* C = a.C + z * a.sC;
     const int i0 = blockIdx.y * GB_M, j0 = blockIdx.x * GB_N;
+    // this split's share of K, in whole k-tiles
+    const int ktiles = (a.K + GB_K - 1) / GB_K;
+    const int per = (ktiles + a.splits - 1) / a.splits;
+    const int kbeg = sp * per * GB_K;
+    int kend = (sp + 1) * per * GB_K;
+    if (kend > a.K) kend = a.K;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
     f32x16 acc;
     #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 
-    for (int k0 = 0; k0 < a.K; k0 += GB_K) {
+    for (int k0 = kbeg; k0 < kend; k0 += GB_K) {
         // A tile: 64 x 32 values, 8 per thread; consecutive threads walk the
         // contiguous index of the stored matrix
         #pragma unroll
@@ -71,7 +79,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
             if (!a.transA) { ii = idx >> 5; kk = idx & 31; } else { ii = idx & 63; kk = idx >> 6; }
             const int gi = i0 + ii, gk = k0 + kk;
             float v = 0.0f;
-            if (gi < a.M && gk < a.K) v = a.transA ? A[(long long)gk * a.lda + gi] : A[(long long)gi * a.lda + gk];
+            if (gi < a.M && gk < kend) v = a.transA ? A[(long long)gk * a.lda + gi] : A[(long long)gi * a.lda + gk];
             As[ii][kk] = (__bf16)v;
         }
         #pragma unroll
@@ -81,7 +89,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
             if (!a.transB) { jj = idx & 63; kk = idx >> 6; } else { jj = idx >> 5; kk = idx & 31; }
             const int gj = j0 + jj, gk = k0 + kk;
             float v = 0.0f;
-            if (gj < a.N && gk < a.K) v = a.transB ? B[(long long)gj * a.ldb + gk] : B[(long long)gk * a.ldb + gj];
+            if (gj < a.N && gk < kend) v = a.transB ? B[(long long)gj * a.ldb + gk] : B[(long long)gk * a.ldb + gj];
             Bs[jj][kk] = (__bf16)v;
         }
         __syncthreads();
@@ -104,11 +112,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a)
         const int ii = i0 + wi + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int jj = j0 + wj + (lane & 31);
         if (ii < a.M && jj < a.N) {
-            float* c = C + (long long)ii * a.ldc + jj;
-            const float v = a.alpha * acc[r];
-            *c = (a.beta != 0.0f) ? v + a.beta * *c : v;
+            if (a.splits > 1) {
+                a.part[(((long long)z * a.splits + sp) * a.M + ii) * a.N + jj] = acc[r];
+            } else {
+                float* c = C + (long long)ii * a.ldc + jj;
+                const float v = a.alpha * acc[r];
+                *c = (a.beta != 0.0f) ? v + a.beta * *c : v;
+            }
         }
     }
+}
+
+// sum of the split-K parts (fixed order), then alpha and beta
+__global__ void k_gemm_reduce(GemmArgs a, int batch)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long mn = (long long)a.M * a.N;
+    if (i >= mn * batch) return;
+    const long long z = i / mn, e = i % mn;
+    const int ii = (int)(e / a.N), jj = (int)(e % a.N);
+    float s = 0.0f;
+    for (int p = 0; p < a.splits; ++p) s += a.part[(z * a.splits + p) * mn + e];
+    float* c = a.C + z * a.sC + (long long)ii * a.ldc + jj;
+    const float v = a.alpha * s;
+    *c = (a.beta != 0.0f) ? v + a.beta * *c : v;
 }
 
 // ---------------------------------------------------------------------------
@@ -140,6 +167,7 @@ __global__ void k_gelu_bwd(float* d, const float* z, long long n)
 // column sums of a rows x C matrix: per workgroup a chunk of rows, then a
 // second pass over the chunks (fixed order, so the result is reproducible)
 constexpr int CS_CHUNK = 256;
+constexpr long long SPLIT_CAP = 1LL << 22;      // split-K scratch of the network's products (floats)
 __global__ void k_colsum_part(const float* x, long long rows, int C, float* part)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -249,6 +277,7 @@ struct sur_net {
     float* dX;               // (B, 2 modes, C)
     float* dY;               // (B, 2 modes, C)
     float* part;             // reduction partials
+    float* split;            // split-K scratch (SPLIT_CAP floats)
     float* m1;               // Adam moments (n_params each)
     float* m2;
     int last_B;              // batch of the last forward (its activations are kept)
@@ -283,7 +312,7 @@ static int cfg_check(const sur_cfg* c, char* why, size_t n)
 
 struct Sizes {
     long long oW0, ob0, oRr, oRi, oW, ob, oW1, ob1, oW2, ob2, n_params;
-    long long F, G, u, z, X, Y, zh, h, dA, dB, dX, dY, part, m1, m2, total;
+    long long F, G, u, z, X, Y, zh, h, dA, dB, dX, dY, part, split, m1, m2, total;
 };
 
 static Sizes sizes_of(const sur_cfg* c)
@@ -322,6 +351,7 @@ static Sizes sizes_of(const sur_cfg* c)
     const long long npart = chunks * (C > P ? C : P) > (Bn * c->c_out + 255) / 256 ? chunks * (C > P ? C : P)
                                                                                    : (Bn * c->c_out + 255) / 256;
     s.part = w; w += al64(npart + 64);
+    s.split = w; w += SPLIT_CAP;
     s.m1 = w; w += al64(s.n_params);
     s.m2 = w; w += al64(s.n_params);
     s.total = w * 4;
@@ -330,18 +360,33 @@ static Sizes sizes_of(const sur_cfg* c)
 
 static int gemm(hipStream_t st, int transA, int transB, int M, int N, int K, float alpha, const float* A, int lda,
                 long long sA, const float* B, int ldb, long long sB, float beta, float* C, int ldc, long long sC,
-                int batch)
+                int batch, float* split_ws = nullptr)
 {
     if (M <= 0 || N <= 0 || batch <= 0) return SUR_OK;
     GemmArgs a;
+    a.splits = 1;
+    a.part = split_ws;
+    // few output tiles over a long K: split K so that the chip has work
+    const long long tiles = (long long)((M + GB_M - 1) / GB_M) * ((N + GB_N - 1) / GB_N) * batch;
+    if (split_ws && tiles < 128 && K >= 8 * GB_K) {
+        long long sp = 256 / tiles;
+        const long long kt = (K + GB_K - 1) / GB_K;
+        if (sp > kt / 4) sp = kt / 4;
+        while (sp > 1 && sp * (long long)M * N * batch > SPLIT_CAP) --sp;
+        if (sp > 1) a.splits = (int)sp;
+    }
     a.A = A; a.B = B; a.C = C;
     a.M = M; a.N = N; a.K = K;
     a.lda = lda; a.ldb = ldb; a.ldc = ldc;
     a.sA = sA; a.sB = sB; a.sC = sC;
     a.transA = transA; a.transB = transB;
     a.alpha = alpha; a.beta = beta;
-    dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch);
+    dim3 grid((N + GB_N - 1) / GB_N, (M + GB_M - 1) / GB_M, batch * a.splits);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, a);
+    if (a.splits > 1) {
+        const long long n = (long long)M * N * batch;
+        hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, batch);
+    }
     return hipGetLastError() == hipSuccess ? SUR_OK : SUR_EDEVICE;
 }
 
@@ -389,7 +434,7 @@ int sur_init(const sur_cfg* cfg, float* d_params, void* d_ws, size_t bytes, void
     float* w = (float*)d_ws;
     n->F = w + s.F; n->G = w + s.G; n->u = w + s.u; n->z = w + s.z; n->X = w + s.X; n->Y = w + s.Y;
     n->zh = w + s.zh; n->h = w + s.h; n->dA = w + s.dA; n->dB = w + s.dB; n->dX = w + s.dX; n->dY = w + s.dY;
-    n->part = w + s.part; n->m1 = w + s.m1; n->m2 = w + s.m2;
+    n->part = w + s.part; n->split = w + s.split; n->m1 = w + s.m1; n->m2 = w + s.m2;
     n->last_B = 0;
     const long long nm = (long long)cfg->n_points * cfg->modes;
     hipLaunchKernelGGL(k_dft_basis, dim3(nblk(nm, 256)), dim3(256), 0, n->s, n->F, n->G, cfg->n_points, cfg->modes);
@@ -416,7 +461,7 @@ int sur_forward(sur_net* n, int32_t B, const float* d_x, float* d_y)
     float* prm = n->prm;
     int rc = SUR_OK;
     // lift
-    rc |= gemm(n->s, 0, 0, (int)Bn, C, c.c_in, 1.0f, d_x, c.c_in, 0, prm + n->oW0, C, 0, 0.0f, n->u, C, 0, 1);
+    rc |= gemm(n->s, 0, 0, (int)Bn, C, c.c_in, 1.0f, d_x, c.c_in, 0, prm + n->oW0, C, 0, 0.0f, n->u, C, 0, 1, n->split);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(act, 256)), dim3(256), 0, n->s, n->u, prm + n->ob0, (float*)nullptr,
                        Bn, C, 0);
     for (int l = 0; l < c.layers; ++l) {
@@ -427,30 +472,30 @@ int sur_forward(sur_net* n, int32_t B, const float* d_x, float* d_y)
         const float* Ri = prm + n->oRi + (long long)l * c.modes * C * C;
         // X_b = F^T u_b
         rc |= gemm(n->s, 1, 0, M2, C, Np, 1.0f, n->F, M2, 0, ul, C, (long long)Np * C, 0.0f, X, C,
-                   (long long)M2 * C, B);
+                   (long long)M2 * C, B, n->split);
         // per mode m: Yr = Xr Rr - Xi Ri, Yi = Xr Ri + Xi Rr (rows b, stride 2 modes x C)
         const int ldx = M2 * C;
-        rc |= gemm(n->s, 0, 0, B, C, C, 1.0f, X, ldx, 2 * C, Rr, C, (long long)C * C, 0.0f, n->Y, ldx, 2 * C, c.modes);
+        rc |= gemm(n->s, 0, 0, B, C, C, 1.0f, X, ldx, 2 * C, Rr, C, (long long)C * C, 0.0f, n->Y, ldx, 2 * C, c.modes, n->split);
         rc |= gemm(n->s, 0, 0, B, C, C, -1.0f, X + C, ldx, 2 * C, Ri, C, (long long)C * C, 1.0f, n->Y, ldx, 2 * C,
-                   c.modes);
+                   c.modes, n->split);
         rc |= gemm(n->s, 0, 0, B, C, C, 1.0f, X, ldx, 2 * C, Ri, C, (long long)C * C, 0.0f, n->Y + C, ldx, 2 * C,
-                   c.modes);
+                   c.modes, n->split);
         rc |= gemm(n->s, 0, 0, B, C, C, 1.0f, X + C, ldx, 2 * C, Rr, C, (long long)C * C, 1.0f, n->Y + C, ldx,
-                   2 * C, c.modes);
+                   2 * C, c.modes, n->split);
         // z = G Y_b + u W + b
         rc |= gemm(n->s, 0, 0, Np, C, M2, 1.0f, n->G, M2, 0, n->Y, C, (long long)M2 * C, 0.0f, un, C,
-                   (long long)Np * C, B);
+                   (long long)Np * C, B, n->split);
         rc |= gemm(n->s, 0, 0, (int)Bn, C, C, 1.0f, ul, C, 0, prm + n->oW + (long long)l * C * C, C, 0, 1.0f, un, C,
-                   0, 1);
+                   0, 1, n->split);
         const int last = (l == c.layers - 1);
         hipLaunchKernelGGL(k_bias_act, dim3(nblk(act, 256)), dim3(256), 0, n->s, un, prm + n->ob + (long long)l * C,
                            n->z + l * act_max, Bn, C, last ? 0 : 1);
     }
     // projection
     float* uL = n->u + c.layers * act_max;
-    rc |= gemm(n->s, 0, 0, (int)Bn, P, C, 1.0f, uL, C, 0, prm + n->oW1, P, 0, 0.0f, n->h, P, 0, 1);
+    rc |= gemm(n->s, 0, 0, (int)Bn, P, C, 1.0f, uL, C, 0, prm + n->oW1, P, 0, 0.0f, n->h, P, 0, 1, n->split);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(Bn * P, 256)), dim3(256), 0, n->s, n->h, prm + n->ob1, n->zh, Bn, P, 1);
-    rc |= gemm(n->s, 0, 0, (int)Bn, c.c_out, P, 1.0f, n->h, P, 0, prm + n->oW2, c.c_out, 0, 0.0f, d_y, c.c_out, 0, 1);
+    rc |= gemm(n->s, 0, 0, (int)Bn, c.c_out, P, 1.0f, n->h, P, 0, prm + n->oW2, c.c_out, 0, 0.0f, d_y, c.c_out, 0, 1, n->split);
     hipLaunchKernelGGL(k_bias_act, dim3(nblk(Bn * c.c_out, 256)), dim3(256), 0, n->s, d_y, prm + n->ob2,
                        (float*)nullptr, Bn, c.c_out, 0);
     if (rc || hipGetLastError() != hipSuccess) return sfail(n, SUR_EDEVICE, "forward launch failed");
@@ -472,16 +517,16 @@ int sur_backward(sur_net* n, int32_t B, const float* d_x, const float* d_dy, flo
     float* g = d_grad;
     int rc = SUR_OK;
     // projection: y = h W2 + b2, h = gelu(zh), zh = uL W1 + b1
-    rc |= gemm(n->s, 1, 0, P, c.c_out, (int)Bn, 1.0f, n->h, P, 0, d_dy, c.c_out, 0, 0.0f, g + n->oW2, c.c_out, 0, 1);
+    rc |= gemm(n->s, 1, 0, P, c.c_out, (int)Bn, 1.0f, n->h, P, 0, d_dy, c.c_out, 0, 0.0f, g + n->oW2, c.c_out, 0, 1, n->split);
     colsum(n, d_dy, Bn, c.c_out, g + n->ob2, 0.0f);
     float* dh = n->dA;
-    rc |= gemm(n->s, 0, 1, (int)Bn, P, c.c_out, 1.0f, d_dy, c.c_out, 0, prm + n->oW2, c.c_out, 0, 0.0f, dh, P, 0, 1);
+    rc |= gemm(n->s, 0, 1, (int)Bn, P, c.c_out, 1.0f, d_dy, c.c_out, 0, prm + n->oW2, c.c_out, 0, 0.0f, dh, P, 0, 1, n->split);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk(Bn * P, 256)), dim3(256), 0, n->s, dh, n->zh, Bn * P);
     const float* uL = n->u + c.layers * act_max;
-    rc |= gemm(n->s, 1, 0, C, P, (int)Bn, 1.0f, uL, C, 0, dh, P, 0, 0.0f, g + n->oW1, P, 0, 1);
+    rc |= gemm(n->s, 1, 0, C, P, (int)Bn, 1.0f, uL, C, 0, dh, P, 0, 0.0f, g + n->oW1, P, 0, 1, n->split);
     colsum(n, dh, Bn, P, g + n->ob1, 0.0f);
     float* du = n->dB;
-    rc |= gemm(n->s, 0, 1, (int)Bn, C, P, 1.0f, dh, P, 0, prm + n->oW1, P, 0, 0.0f, du, C, 0, 1);
+    rc |= gemm(n->s, 0, 1, (int)Bn, C, P, 1.0f, dh, P, 0, prm + n->oW1, P, 0, 0.0f, du, C, 0, 1, n->split);
     // Fourier layers, last to first; du holds dL/du_{l+1} on entry
     for (int l = c.layers - 1; l >= 0; --l) {
         const float* ul = n->u + l * act_max;
@@ -494,36 +539,36 @@ int sur_backward(sur_net* n, int32_t B, const float* d_x, const float* d_dy, flo
         if (l != c.layers - 1)
             hipLaunchKernelGGL(k_gelu_bwd, dim3(nblk(act, 256)), dim3(256), 0, n->s, dz, n->z + l * act_max, act);
         colsum(n, dz, Bn, C, g + n->ob + (long long)l * C, 0.0f);
-        rc |= gemm(n->s, 1, 0, C, C, (int)Bn, 1.0f, ul, C, 0, dz, C, 0, 0.0f, g + n->oW + (long long)l * C * C, C, 0, 1);
+        rc |= gemm(n->s, 1, 0, C, C, (int)Bn, 1.0f, ul, C, 0, dz, C, 0, 0.0f, g + n->oW + (long long)l * C * C, C, 0, 1, n->split);
         // dY_b = G^T dz_b
         rc |= gemm(n->s, 1, 0, M2, C, Np, 1.0f, n->G, M2, 0, dz, C, (long long)Np * C, 0.0f, n->dY, C,
-                   (long long)M2 * C, B);
+                   (long long)M2 * C, B, n->split);
         const int ldx = M2 * C;
         const float* dYr = n->dY;
         const float* dYi = n->dY + C;
         const float* Xr = X;
         const float* Xi = X + C;
         // dRr = Xr^T dYr + Xi^T dYi, dRi = Xr^T dYi - Xi^T dYr (per mode)
-        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xr, ldx, 2 * C, dYr, ldx, 2 * C, 0.0f, gRr, C, (long long)C * C, c.modes);
-        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xi, ldx, 2 * C, dYi, ldx, 2 * C, 1.0f, gRr, C, (long long)C * C, c.modes);
-        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xr, ldx, 2 * C, dYi, ldx, 2 * C, 0.0f, gRi, C, (long long)C * C, c.modes);
-        rc |= gemm(n->s, 1, 0, C, C, B, -1.0f, Xi, ldx, 2 * C, dYr, ldx, 2 * C, 1.0f, gRi, C, (long long)C * C, c.modes);
+        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xr, ldx, 2 * C, dYr, ldx, 2 * C, 0.0f, gRr, C, (long long)C * C, c.modes, n->split);
+        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xi, ldx, 2 * C, dYi, ldx, 2 * C, 1.0f, gRr, C, (long long)C * C, c.modes, n->split);
+        rc |= gemm(n->s, 1, 0, C, C, B, 1.0f, Xr, ldx, 2 * C, dYi, ldx, 2 * C, 0.0f, gRi, C, (long long)C * C, c.modes, n->split);
+        rc |= gemm(n->s, 1, 0, C, C, B, -1.0f, Xi, ldx, 2 * C, dYr, ldx, 2 * C, 1.0f, gRi, C, (long long)C * C, c.modes, n->split);
         // dXr = dYr Rr^T + dYi Ri^T, dXi = dYi Rr^T - dYr Ri^T
-        rc |= gemm(n->s, 0, 1, B, C, C, 1.0f, dYr, ldx, 2 * C, Rr, C, (long long)C * C, 0.0f, n->dX, ldx, 2 * C, c.modes);
-        rc |= gemm(n->s, 0, 1, B, C, C, 1.0f, dYi, ldx, 2 * C, Ri, C, (long long)C * C, 1.0f, n->dX, ldx, 2 * C, c.modes);
+        rc |= gemm(n->s, 0, 1, B, C, C, 1.0f, dYr, ldx, 2 * C, Rr, C, (long long)C * C, 0.0f, n->dX, ldx, 2 * C, c.modes, n->split);
+        rc |= gemm(n->s, 0, 1, B, C, C, 1.0f, dYi, ldx, 2 * C, Ri, C, (long long)C * C, 1.0f, n->dX, ldx, 2 * C, c.modes, n->split);
         rc |= gemm(n->s, 0, 1, B, C, C, 1.0f, dYi, ldx, 2 * C, Rr, C, (long long)C * C, 0.0f, n->dX + C, ldx, 2 * C,
-                   c.modes);
+                   c.modes, n->split);
         rc |= gemm(n->s, 0, 1, B, C, C, -1.0f, dYr, ldx, 2 * C, Ri, C, (long long)C * C, 1.0f, n->dX + C, ldx, 2 * C,
-                   c.modes);
+                   c.modes, n->split);
         // du_l = dz W^T + F dX_b  (into the other scratch, then swap)
         float* dn = (du == n->dB) ? n->dA : n->dB;
-        rc |= gemm(n->s, 0, 1, (int)Bn, C, C, 1.0f, dz, C, 0, prm + n->oW + (long long)l * C * C, C, 0, 0.0f, dn, C, 0, 1);
+        rc |= gemm(n->s, 0, 1, (int)Bn, C, C, 1.0f, dz, C, 0, prm + n->oW + (long long)l * C * C, C, 0, 0.0f, dn, C, 0, 1, n->split);
         rc |= gemm(n->s, 0, 0, Np, C, M2, 1.0f, n->F, M2, 0, n->dX, C, (long long)M2 * C, 1.0f, dn, C,
-                   (long long)Np * C, B);
+                   (long long)Np * C, B, n->split);
         du = dn;
     }
     // lift: u0 = x W0 + b0
-    rc |= gemm(n->s, 1, 0, c.c_in, C, (int)Bn, 1.0f, d_x, c.c_in, 0, du, C, 0, 0.0f, g + n->oW0, C, 0, 1);
+    rc |= gemm(n->s, 1, 0, c.c_in, C, (int)Bn, 1.0f, d_x, c.c_in, 0, du, C, 0, 0.0f, g + n->oW0, C, 0, 1, n->split);
     colsum(n, du, Bn, C, g + n->ob0, 0.0f);
     if (rc || hipGetLastError() != hipSuccess) return sfail(n, SUR_EDEVICE, "backward launch failed");
     return SUR_OK;

@@ -189,13 +189,15 @@ def train(x, t, m, steps=2000, batch=32, lr=1e-3, seed=5, net=None, log=None):
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
     n = x.shape[0]
+    t0 = time.perf_counter()
     for it in range(steps):
         idx = torch.randint(0, n, (batch,), generator=g).to(dev)
         xb, tb, mb = x[idx].contiguous(), t[idx].contiguous(), m[idx].contiguous()
         step_lr = lr if it < steps // 2 else lr * 0.5 ** (1 + 4 * (it - steps // 2) // steps)
         loss = net.train_step(xb, tb, wo, mb, lr=step_lr)
         if log and (it % 500 == 0 or it == steps - 1):
-            log(f"[sweep] step {it}: loss {float(loss.cpu()[0]):.3e}")
+            log(f"[sweep] step {it}: loss {float(loss.cpu()[0]):.3e} ({(time.perf_counter() - t0) / (it + 1) * 1e3:.2f} "
+                f"ms per step)")
     return net
 
 
