@@ -38,6 +38,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched sweep")
     ap.add_argument("--batch-seed", type=int, default=7)
     ap.add_argument("--no-batch", action="store_true", help="leave the batched sweep out of the default line")
+    ap.add_argument("--no-sweep", action="store_true", help="leave the surrogate sweep out of the default line")
+    ap.add_argument("--sweep-train", type=int, default=2048, help="training instances of the surrogate")
+    ap.add_argument("--sweep-steps", type=int, default=3000, help="Adam steps of the surrogate")
+    ap.add_argument("--sweep-points", type=int, default=1024, help="points of the surrogate sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=600, help="rows past D in the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -164,13 +168,88 @@ def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
     bat.close()
     del ws
     torch.cuda.empty_cache()
+    # algorithmic HBM bytes of the march: per cell 16 B written and 16 B of the
+    # delay row read, plus 32 B per strip cell of mirror reads
+    hbm = float(sum(32.0 * (i.Nx + i.D) * i.Nt for i in insts))
+    gbs = hbm / (tm / steps * 1e-3) / 1e9
     return {"instances": n, "seed": seed, "cells": cells, "s_per_step": sec, "cell_updates_per_s": cells / sec,
+            "march_algorithmic_GBps": gbs, "march_hbm_frac": gbs / HBM_PEAK_GBS,
             "instances_per_s": n / sec, "march_ms": tm / steps, "boundary_ms": tb / steps,
             "march_cell_updates_per_s": cells / (tm / steps * 1e-3), "launches": info["launches"],
             "max_workgroups_per_launch": info["max_workgroups"],
             "autotune": {"tmax": best.tmax, "wmax": best.wmax, "graph": bool(best.use_graph),
                          "probe_rate": rate, "seconds": t_tune},
             "ring_GB": sum((i.D + 2 * best.tmax + 2) * (i.Nx + 1) * 16 for i in insts) / 1e9}
+
+
+def run_sweep(n_train: int, n_pts: int, steps: int, tol: float = 1e-3) -> dict:
+    """Surrogate training and the surrogate-with-fallback sweep against the
+    plain batched solver, on points drawn from the batched sweep's
+    distribution.  Points/s count every step each path takes for the points
+    (the surrogate path: input encoding, inference, coarse-grid check, FP64
+    re-solve of the rejected points); training is reported on its own."""
+    import numpy as np
+    import torch
+
+    from paper_1707_05943_amd import sweep as SW
+    from paper_1707_05943_amd import workloads as W
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    solver = SW.Solver()
+    t0 = time.perf_counter()
+    x, t, m = SW.make_dataset(W.sweep_draw(n_train, 101), solver, chunk=512)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    net = SW.train(x, t, m, steps=steps, batch=32, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del x, t, m
+    pts = W.sweep_draw(n_pts, 202)
+    ta = time.perf_counter()
+    plain = torch.cat([solver.solve(pts[s:s + 512], with_chi=False)[0] for s in range(0, n_pts, 512)])
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    out, ok, info = SW.sweep(pts, net, solver, tol=tol, log=log)
+    err = SW.rel_err(out, plain)
+    s_err = SW.rel_err(SW.predict_pe(net, SW.features(pts, solver.device)), plain)
+    acc = ok.cpu().numpy()
+    e = err.cpu().numpy()
+    # the method without the network: the same points on coarser grids only
+    coarse = {}
+    for f in (2, 4):
+        cs = [SW.coarse(p, f) for p in pts]
+        ids = [i for i, c in enumerate(cs) if c is not None]
+        tc = time.perf_counter()
+        pe = torch.cat([solver.solve([cs[i] for i in ids[s:s + 512]], with_chi=False,
+                                     t_end=[SW.pe_window(pts[i]) for i in ids[s:s + 512]])[0]
+                        for s in range(0, len(ids), 512)])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - tc
+        ce = SW.rel_err(pe, plain[torch.tensor(ids, device=plain.device)]).cpu().numpy()
+        coarse[str(f)] = {"points": len(ids), "points_per_s": len(ids) / dt,
+                          "frac_within_tol": float((ce <= tol).mean()), "median_rel_err": float(np.median(ce))}
+    # surrogate inference alone on a larger draw
+    big = W.sweep_draw(16384, 303)
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
+    xb = torch.cat([SW.features(big[s:s + 4096], solver.device) for s in range(0, len(big), 4096)])
+    SW.predict_pe(net, xb)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - ti
+    solver.ws = None
+    torch.cuda.empty_cache()
+    return {"tol": tol, "points": n_pts, "seed_points": 202,
+            "plain_points_per_s": n_pts / (tb - ta),
+            "surrogate_with_fallback_points_per_s": n_pts / info["total_s"],
+            "accepted": int(acc.sum()), "fallback": info["fallback"],
+            "accepted_true_err_above_tol": int(((e > tol) & acc).sum()),
+            "max_true_err": float(e.max()), "surrogate_alone_median_rel_err": float(np.median(s_err.cpu().numpy())),
+            "surrogate_alone_p90_rel_err": float(np.quantile(s_err.cpu().numpy(), 0.9)),
+            "timing_s": {k: info[k] for k in ("surrogate_s", "check_s", "fallback_s", "total_s")},
+            "inference_points_per_s": len(big) / t_inf,
+            "plain_on_coarser_grid": coarse,
+            "training": {"instances": n_train, "data_s": t1 - t0, "steps": steps, "train_s": t2 - t1,
+                         "ms_per_step": (t2 - t1) / steps * 1e3, "batch": 32}}
 
 
 def main():
@@ -265,6 +344,18 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows)
+    if args.workload == "large" and not args.no_batch:
+        print(f"[bench] batched sweep of {args.batch} instances", file=sys.stderr, flush=True)
+        try:
+            out["batch"] = run_batch(args.batch, args.batch_seed, max(1, args.steps - 1), 1)
+        except Exception as e:                                  # the headline line is printed regardless
+            out["batch"] = {"error": f"{type(e).__name__}: {e}"}
+    if args.workload == "large" and not args.no_sweep:
+        print("[bench] surrogate sweep", file=sys.stderr, flush=True)
+        try:
+            out["sweep"] = run_sweep(args.sweep_train, args.sweep_points, args.sweep_steps)
+        except Exception as e:
+            out["sweep"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out), flush=True)
 
 
