@@ -129,6 +129,7 @@ struct Plan {
     int64_t win_lo;      // first strip column kept in the LDS window of the current block
     int nwg;             // Gs + Gm
     int nb;              // launched blocks (a multiple of 8, >= nwg)
+    int nst;             // doubling stages of the within-row scan inside 16-lane rows (2^nst K > H, <= 4)
 };
 
 struct fdtd_ctx {

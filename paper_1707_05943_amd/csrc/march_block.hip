@@ -126,13 +126,19 @@ __device__ void fill_pow(cd al, Pow& p)
     }
 }
 
-// inclusive scan over a wave of x_l = v_l + alpha^K x_{l-1}
-__device__ __forceinline__ cd wave_scan(cd x, const Pow& P, int lane)
+// inclusive scan over a wave of x_l = v_l + alpha^K x_{l-1}.  Inside each
+// row of 16 lanes only the first `nst` doubling stages run: lane l then sums
+// lanes l - 2^nst + 1 .. l of its row, the older terms carrying
+// alpha^(K 2^nst) or less, below 2^-60 relative when 2^nst K exceeds the
+// recurrence's horizon H.  The two row-crossing stages always run, so the
+// first lanes of a row take the previous row's last lane (nst is uniform:
+// the branches do not diverge).
+__device__ __forceinline__ cd wave_scan(cd x, const Pow& P, int lane, int nst)
 {
-    x += P.s[0] * dpp_cd<DPP_ROW_SHR1, 0xF>(x);
-    x += P.s[1] * dpp_cd<DPP_ROW_SHR2, 0xF>(x);
-    x += P.s[2] * dpp_cd<DPP_ROW_SHR4, 0xF>(x);
-    x += P.s[3] * dpp_cd<DPP_ROW_SHR8, 0xF>(x);
+    if (nst > 0) x += P.s[0] * dpp_cd<DPP_ROW_SHR1, 0xF>(x);
+    if (nst > 1) x += P.s[1] * dpp_cd<DPP_ROW_SHR2, 0xF>(x);
+    if (nst > 2) x += P.s[2] * dpp_cd<DPP_ROW_SHR4, 0xF>(x);
+    if (nst > 3) x += P.s[3] * dpp_cd<DPP_ROW_SHR8, 0xF>(x);
     x += P.m15[lane] * dpp_cd<DPP_ROW_BCAST15, 0xA>(x);
     x += P.m31[lane] * dpp_cd<DPP_ROW_BCAST31, 0xC>(x);
     return x;
@@ -235,7 +241,7 @@ __device__ __forceinline__ void load_mirror(const Geom& g, const Bufs& b, int64_
 template <bool FAR>
 __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win& W, const Pow& P, const Seg& S,
                                          Lane& L, cd (*wave_tot)[NW], const RowInfo& ri, const RowInfo* rnext,
-                                         int64_t r, int64_t rb, int64_t act_lo, int par)
+                                         int64_t r, int64_t rb, int64_t act_lo, int par, int nst)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t j0 = S.lo + (int64_t)(tid - S.t0) * K;
@@ -331,12 +337,13 @@ __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win
     // x_t = u_last + alpha^K x_{t-1}: inclusive scan over the segment's threads
     cd x = u[K - 1];
     if (tid == S.t0) x += P.a[K] * carry0;
-    x = wave_scan(x, P, lane);
+    x = wave_scan(x, P, lane, nst);
     if (lane == 63) wave_tot[par][wv] = x;
     const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
     __syncthreads();
-    cd wcarry = zero();
-    for (int w2 = S.w0; w2 < wv; ++w2) wcarry = P.m64 * wcarry + wave_tot[par][w2];
+    // the previous wave's last lane; waves further left enter with at least
+    // alpha^(64 K), below 2^-60 relative for every admissible alpha
+    const cd wcarry = (wv > S.w0) ? wave_tot[par][wv - 1] : zero();
     // the value just left of this thread's first column
     cd cin = prevx + P.lp[lane] * wcarry;
     if (tid == S.t0) cin = carry0;
@@ -416,7 +423,7 @@ __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64
 template <bool FAR>
 __device__ __forceinline__ void march_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw, const Seg& S,
                                            cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
-                                           int64_t ra, int64_t rb, int H1, int T, int cone, int use_win)
+                                           int64_t ra, int64_t rb, int H1, int T, int cone, int use_win, int nst)
 {
     Lane L;
     load_base(g, b, S, L, ra, rinfo[0]);
@@ -427,7 +434,7 @@ __device__ __forceinline__ void march_rows(const Geom& g, const Bufs& b, const W
         if (cone && threadIdx.x >= NT / 2 && tau > T - 2) act = S.hi;     // the cone stops a row early
         const RowInfo ri = rinfo[tau];
         const RowInfo* rn = &rinfo[tau + 1 < BM_TMAX ? tau + 1 : tau];
-        double pe = do_row<FAR>(g, b, W, pw, S, L, wave_tot, ri, rn, r, rb, act, par);
+        double pe = do_row<FAR>(g, b, W, pw, S, L, wave_tot, ri, rn, r, rb, act, par, nst);
         pe = wave_sum63(pe);
         if ((threadIdx.x & 63) == 63) pe_lds[tau][threadIdx.x >> 6] = pe;
         if (use_win) __syncthreads();            // window rows written above are read by the next row
@@ -551,8 +558,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.lo = P.win_lo;
     W.row0 = ra;
 
-    if (far) march_rows<true>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win);
-    else march_rows<false>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win);
+    if (far) march_rows<true>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win, P.nst);
+    else march_rows<false>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win, P.nst);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
@@ -618,7 +625,7 @@ int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipS
 // the near part of the outgoing region -- count MIRROR_COST times a far
 // column), about kn.ncu workgroups (one per compute unit for an instance that
 // runs alone; an instance of a batch asks for the widest workgroups).
-static const double MIRROR_COST = 2.0;
+static const double MIRROR_COST = 3.5;
 
 int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char* why, size_t n)
 {
@@ -696,6 +703,11 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
         // halos start right of column 0
         if (P.Gn > 1 && D + 1 + P.near_w - P.hmax < 1) continue;
         P.win_lo = D - T + 1 < 1 ? 1 : D - T + 1;
+        // scan stages inside a row of 16 lanes: a lane needs the carries of
+        // ceil(H / K) lanes to its left
+        const int look = (H + BM_K - 1) / BM_K;
+        P.nst = 0;
+        while (P.nst < 4 && (1 << P.nst) < look + 1) ++P.nst;
         P.nb = ((P.nwg + 7) / 8) * 8;
         *out = P;
         return FDTD_OK;
