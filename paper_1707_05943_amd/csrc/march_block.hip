@@ -71,13 +71,15 @@ __device__ inline cd rd(const Geom& g, const Bufs& b, int64_t i, int64_t rho)
 }
 
 // cross-lane moves with DPP (GFX9 encodings); lanes without a source get 0
+// (bound_ctrl), every row is written: the row-broadcast stages' multipliers
+// are zero on the rows a broadcast must not change
 template <int CTRL, int RM>
 __device__ __forceinline__ double dpp_f64(double v)
 {
     const long long bits = __double_as_longlong(v);
     int lo = (int)(unsigned)(bits & 0xffffffffLL), hi = (int)(bits >> 32);
-    lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xF, false);
-    hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xF, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, true);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 template <int CTRL, int RM>
@@ -171,6 +173,10 @@ struct RowInfo {
     cd half_qr;                  // (Phi[r-D] + Phi[r-D-1]) / 2
     cd drv;                      // drive factor of row r
     int delay_on;                // r - 1 >= D
+    // far columns: S / d = g8r dsum + krc (Et[q] - Et[q+D]) + drc Phi[q]
+    cd g8r;                      // cinv Gamma/8 (0 before the delay starts)
+    cd krc;                      // cinv (-Gamma/2) (half_pr - half_qr)
+    cd drc;                      // cinv drv
 };
 
 // A thread's column range and role.  Threads t0 .. t0+nt-1 of the workgroup
@@ -382,6 +388,134 @@ __device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win
     return pe;
 }
 
+// acc += a b with four fused multiply-adds
+__device__ __forceinline__ void cmac(cd& acc, const cd a, const cd b)
+{
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The rows of a workgroup whose every column lies beyond 2D: all source
+// terms are exact (tables Et[q] - Et[q+D] and Phi[q] in LDS), the delay rows
+// are the only reads of the ring.  The workgroup's range starts a halo left
+// of its own columns (the trapezoid moves H+1 columns right per row), so the
+// carry into its first column is zero.  Rows go in threes so that the three
+// delay-row buffers rotate instead of being copied.
+__device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
+                                         const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
+                                         int64_t rb, int H1, int nst)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t D = g.D, C = g.C;
+    const int64_t j0 = S.lo + (int64_t)K * tid;
+    const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
+    const bool live = j0 <= jmax;
+    const unsigned own = (unsigned)(j0 * 16);                 // byte offset of column j0 in a row
+    const unsigned dly = (unsigned)((j0 - 1 - D) * 16);       // ... of column j0-1-D (>= 1: j0 > 2D)
+    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    const cd lp = pw.lp[lane];
+    const cd* tE = S.tE;
+    const cd* tP = S.tP;
+
+    // ring slot sl (< 0: a row before t = 0) as a base pointer in scalar registers
+    auto ring_row = [&](int64_t sl) -> const char* {
+        return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
+    };
+    auto load4 = [&](cd (&dst)[K + 1], int64_t sl) {
+        if (uni((int)sl) < 0 || !live) {
+            #pragma unroll
+            for (int i = 0; i <= K; ++i) dst[i] = zero();
+            return;
+        }
+        const char* rp = ring_row(sl) + dly;
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
+    };
+
+    // the base row ra-1 (own columns and the one to the left) and the delay
+    // rows of row ra
+    cd up[K + 1];
+    {
+        const char* rp = ring_row((ra - 1) % g.R) + own;
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) {
+            const int64_t j = j0 - 1 + i;
+            up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
+        }
+    }
+    cd X[K + 1], Y[K + 1], Z[K + 1];
+    load4(X, slot_or_neg(ra - 1 - D, g.R));
+    load4(Y, slot_or_neg(ra - D, g.R));
+
+    auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
+        const int tau = (int)(r - ra);
+        const int par = tau & 1;
+        const RowInfo& ri = rinfo[tau];
+        const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
+        if (r + 1 <= rb) load4(N, ri.slot_pf);
+        // beta of the three columns
+        cd p[K + 1];
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) p[i] = A[i] + Bv[i];
+        const int64_t t0 = r - j0 - S.qa;
+        const cd g8r = ri.g8r, krc = ri.krc, drc = ri.drc;
+        cd u[K];
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            cd v = zero();
+            cmac(v, cA, up[i]);
+            cmac(v, cB, up[i + 1]);
+            cmac(v, g8r, p[i] + p[i + 1]);
+            const int64_t t = live ? t0 - i : 0;
+            cmac(v, krc, tE[t]);
+            cmac(v, drc, tP[t]);
+            u[i] = (j >= act_lo && j <= jmax) ? v : zero();
+        }
+        cmac(u[1], al, u[0]);
+        cmac(u[2], al, u[1]);
+        // carries across threads and waves
+        cd x = wave_scan(u[K - 1], pw, lane, nst);
+        if (lane == 63) wave_tot[par][wv] = x;
+        const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
+        __syncthreads();
+        cd cin = prevx;
+        if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
+        // the row's values, the ring, P_e
+        char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
+        double pe = 0.0;
+        up[0] = cin;
+        const cd ap[K] = {a1, a2, a3};
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const bool act = (j >= act_lo && j <= jmax);
+            cd v = u[i];
+            cmac(v, ap[i], cin);
+            v = act ? v : zero();
+            up[i + 1] = v;
+            if (act && j >= S.own_lo) {
+                *reinterpret_cast<cd*>(wp + 16 * i) = v;
+                const double m2 = norm2(v);
+                pe += (j == g.Nx) ? 0.5 * m2 : m2;
+            }
+        }
+        pe = wave_sum63(pe);
+        if (lane == 63) pe_lds[tau][wv] = pe;
+    };
+
+    for (int64_t r = ra; r <= rb; r += 3) {
+        step(r, X, Y, Z);
+        if (r + 1 <= rb) step(r + 1, Y, Z, X);
+        if (r + 2 <= rb) step(r + 2, Z, X, Y);
+    }
+}
+
 // the block's base row (row r0-1), the delay rows and mirror values of its first row
 __device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Seg& S, Lane& L, int64_t r0,
                                           const RowInfo& ri0)
@@ -540,6 +674,9 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         ri.half_qr = 0.5 * (phi_at(b, r - D) + phi_at(b, r - D - 1));
         ri.drv = b.Drv[r];
         ri.delay_on = (r - 1 >= D);
+        ri.g8r = ri.delay_on ? (0.125 * g.Gamma) * g.cinv : zero();
+        ri.krc = g.cinv * ((-0.5 * g.Gamma) * (ri.half_pr - ri.half_qr));
+        ri.drc = g.cinv * ri.drv;
         rinfo[threadIdx.x] = ri;
     }
     fill_pow(g.alpha, pw);
@@ -558,7 +695,7 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.lo = P.win_lo;
     W.row0 = ra;
 
-    if (far) march_rows<true>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win, P.nst);
+    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
     else march_rows<false>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win, P.nst);
     __syncthreads();
     if (threadIdx.x < nrows) {
