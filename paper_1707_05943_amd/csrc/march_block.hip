@@ -51,7 +51,7 @@ namespace {
 constexpr int NT = BM_THREADS;
 constexpr int K = BM_K;
 constexpr int NW = NT / 64;
-constexpr int TBL = 1600;                  // LDS table entries (>= BM_CAP + BM_TMAX, and 2 x (NT/2 K + BM_TMAX))
+constexpr int TBL = 1608;                  // LDS table entries (>= BM_CAP + BM_TMAX + 2, and 2 x (NT/2 K + BM_TMAX + 2))
 
 __device__ inline cd zero() { return mk(0.0, 0.0); }
 __device__ inline int64_t dec_slot(int64_t s, int64_t R) { return s == 0 ? R - 1 : s - 1; }
@@ -177,6 +177,10 @@ struct RowInfo {
     cd g8r;                      // cinv Gamma/8 (0 before the delay starts)
     cd krc;                      // cinv (-Gamma/2) (half_pr - half_qr)
     cd drc;                      // cinv drv
+    // strip columns: their delay corners lie at x <= -a, psi = Phi Et there
+    cd ga, gb;                   // g8r Et[r-1-D], g8r Et[r-D]
+    cd hp;                       // cinv (-Gamma/2) half_pr
+    cd psi0;                     // psi(0, r) = Phi[r] Et[r]
 };
 
 // A thread's column range and role.  Threads t0 .. t0+nt-1 of the workgroup
@@ -516,6 +520,308 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     }
 }
 
+// The rows of a near workgroup (columns D+1 .. 2D + hmax).  The delay
+// corners are ring values (column 0, which only the region's first column
+// reads, is the exact solution); the first source term is exact, the second
+// reads the mirror pair psi(2D-j, q+D), psi(2D-j+1, q+D) from the diagonal
+// copy for j < 2D, with psi(0, q+D) exact at j = 2D and both exact beyond.
+__device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
+                                          const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
+                                          int64_t rb, int H1, int nst)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t D = g.D, C = g.C, Mc = g.Mc;
+    const int64_t j0 = S.lo + (int64_t)K * tid;
+    const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
+    const bool live = j0 <= jmax;
+    const int64_t dcol = j0 - 1 - D;                          // first delay column (0 only for j0 = D+1)
+    const unsigned dly = (unsigned)(dcol * 16);
+    const unsigned own = (unsigned)(j0 * 16);
+    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd c4 = (0.25 * g.Gamma) * g.cinv;
+    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    const cd lp = pw.lp[lane];
+    const cd* tE = S.tE;
+    const cd* tP = S.tP;
+    const cd* tE2 = S.tE2;
+    const bool first = (tid == 0);
+
+    auto ring_row = [&](int64_t sl) -> const char* {
+        return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
+    };
+    // delay row rho (ring slot sl; sl < 0 before t = 0)
+    auto load4 = [&](cd (&dst)[K + 1], int64_t sl, int64_t rho) {
+        const int s32 = uni((int)sl);
+        const bool ok = s32 >= 0 && live;
+        const char* rp = ring_row(s32 < 0 ? 0 : s32) + dly;
+        cd v[K + 1];
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) v[i] = ok ? *reinterpret_cast<const cd*>(rp + 16 * i) : zero();
+        cd e0 = zero();
+        if (ok && dcol == 0) e0 = b.Phi[rho] * b.Et[rho];
+        dst[0] = (dcol == 0) ? e0 : v[0];
+        #pragma unroll
+        for (int i = 1; i <= K; ++i) dst[i] = v[i];
+    };
+    // mirror pair of row r for the cells with j < 2D (j = 2D: only the second)
+    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB) {
+        const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
+        const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t c = 2 * D - (j0 + i);
+            const bool ok = live && j0 + i <= jmax && c >= 0;
+            mA[i] = (ok && c >= 1) ? rA[c] : zero();
+            mB[i] = ok ? rB[c + 1] : zero();
+        }
+    };
+
+    cd up[K + 1];
+    {
+        const char* rp = ring_row((ra - 1) % g.R) + own;
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) {
+            const int64_t j = j0 - 1 + i;
+            up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
+        }
+    }
+    cd X[K + 1], Y[K + 1], Z[K + 1];
+    load4(X, slot_or_neg(ra - 1 - D, g.R), ra - 1 - D);
+    load4(Y, slot_or_neg(ra - D, g.R), ra - D);
+    cd mA[K], mB[K], nA[K], nB[K];
+    load_m(mA, mB, rinfo[0].slot, rinfo[0].slot_m1);
+
+    auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
+        const int tau = (int)(r - ra);
+        const int par = tau & 1;
+        const RowInfo& ri = rinfo[tau];
+        const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
+        if (r + 1 <= rb) {
+            load4(N, ri.slot_pf, r + 1 - D);
+            const RowInfo& rn = rinfo[tau + 1];
+            load_m(nA, nB, rn.slot, rn.slot_m1);
+        }
+        cd p[K + 1];
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) p[i] = A[i] + Bv[i];
+        const int64_t t0 = r - j0 - S.qa;
+        const cd g8r = ri.g8r, krc = ri.krc, drc = ri.drc, hp = ri.hp;
+        cd u[K];
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const int64_t q = r - j;
+            const bool cell = (j >= act_lo && j <= jmax);
+            const int64_t t = live ? t0 - i : 0;
+            const cd et = tE[t], ph = tP[t], et2 = tE2[t];
+            cd v = zero();
+            cmac(v, cA, up[i]);
+            cmac(v, cB, up[i + 1]);
+            cmac(v, g8r, p[i] + p[i + 1]);
+            cmac(v, krc, et);                           // first source, exact
+            cmac(v, drc, ph);
+            if (j <= 2 * D) {
+                // second source: -(G/2)[ (m0 + m1)/2 - Et[q+D] half_pr ]
+                cd ph2 = zero();
+                if (j == 2 * D && q + D >= 0) ph2 = b.Phi[q + D];
+                const cd m0 = (j == 2 * D) ? ph2 * et2 : mA[i];
+                cmac(v, -c4, (q + D >= 0) ? m0 + mB[i] : zero());
+                cmac(v, -hp, et2);
+            } else {
+                cmac(v, -krc, et2);                     // both parts exact
+            }
+            u[i] = cell ? v : zero();
+        }
+        cmac(u[1], al, u[0]);
+        cmac(u[2], al, u[1]);
+        cd x = u[K - 1];
+        cd carry0 = zero();
+        if (first && S.exact) {
+            carry0 = *reinterpret_cast<const cd*>(ring_row(ri.slot) + (unsigned)((S.lo - 1) * 16));
+            cmac(x, a3, carry0);
+        }
+        x = wave_scan(x, pw, lane, nst);
+        if (lane == 63) wave_tot[par][wv] = x;
+        const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
+        __syncthreads();
+        cd cin = prevx;
+        if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
+        if (first) cin = carry0;
+        char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
+        double pe = 0.0;
+        up[0] = cin;
+        const cd ap[K] = {a1, a2, a3};
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const bool act = (j >= act_lo && j <= jmax);
+            cd v = u[i];
+            cmac(v, ap[i], cin);
+            v = act ? v : zero();
+            up[i + 1] = v;
+            if (act && j >= S.own_lo) {
+                *reinterpret_cast<cd*>(wp + 16 * i) = v;
+                const double m2 = norm2(v);
+                pe += (j == g.Nx) ? 0.5 * m2 : m2;
+            }
+        }
+        pe = wave_sum63(pe);
+        if (lane == 63) pe_lds[tau][wv] = pe;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            mA[i] = nA[i];
+            mB[i] = nB[i];
+        }
+    };
+
+    for (int64_t r = ra; r <= rb; r += 3) {
+        step(r, X, Y, Z);
+        if (r + 1 <= rb) step(r + 1, Y, Z, X);
+        if (r + 2 <= rb) step(r + 2, Z, X, Y);
+    }
+}
+
+// The rows of a segment of strip columns (1 <= j <= D): the strip's own
+// workgroups and the cone.  A strip cell's four delay corners lie at
+// x <= -a, so with q = r - j they are Et[r-1-D] (Phi[q] + Phi[q-1]) and
+// Et[r-D] (Phi[q+1] + Phi[q]) from the LDS table; the mirror reads
+// psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (prefetched a row
+// ahead) or, for the strip's first columns, from the LDS window of the
+// current block.  The table here starts one entry before q = S.qa + 1.
+__device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw,
+                                           cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
+                                           const Seg& S, int64_t ra, int64_t rb, int H1, int T, int cone,
+                                           int use_win, int nst)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t D = g.D, C = g.C, Mc = g.Mc;
+    const int64_t j0 = S.lo + (int64_t)K * (tid - S.t0);
+    const int64_t jmax = (S.hi - 1 < D) ? S.hi - 1 : D;
+    const bool live = j0 <= jmax;
+    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd c4 = (0.25 * g.Gamma) * g.cinv;
+    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    const cd lp = pw.lp[lane];
+    const cd* tE = S.tE;
+    const cd* tP = S.tP;
+    const bool first = (tid == S.t0);
+
+    // mirror values of row r for this thread's cells: diagonals r-D (Md row
+    // slot(r)) at column D-j, and r-D-1 (slot(r-1)) at column D-j+1
+    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB) {
+        const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
+        const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t c = D - (j0 + i);
+            const bool ok = live && j0 + i <= jmax;
+            mA[i] = (ok && c >= 1) ? rA[c] : zero();
+            mB[i] = ok ? rB[c + 1] : zero();
+        }
+    };
+
+    cd up[K + 1];
+    {
+        const cd* rp = b.ring + (int64_t)uni((int)((ra - 1) % g.R)) * C;
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) {
+            const int64_t j = j0 - 1 + i;
+            up[i] = (live && j <= jmax) ? (j >= 1 ? rp[j] : phi_at(b, ra - 1) * et_at(b, ra - 1)) : zero();
+        }
+    }
+    cd MA0[K], MB0[K], MA1[K], MB1[K];
+    load_m(MA0, MB0, rinfo[0].slot, rinfo[0].slot_m1);
+    const int64_t R = g.R;
+    int64_t sdr = ((ra - j0 + D) % R + R) % R;                  // Md row of diagonal r - j0, row by row
+
+    auto step = [&](int64_t r, const cd (&mA)[K], const cd (&mB)[K], cd (&nA)[K], cd (&nB)[K]) {
+        const int tau = (int)(r - ra);
+        const int par = tau & 1;
+        const RowInfo& ri = rinfo[tau];
+        int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
+        if (cone && tid >= NT / 2 && tau > T - 2) act_lo = S.hi;        // the cone stops a row early
+        if (r + 1 <= rb) {
+            const RowInfo& rn = rinfo[tau + 1];
+            load_m(nA, nB, rn.slot, rn.slot_m1);
+        }
+        const cd ga = ri.ga, gb = ri.gb, hp = ri.hp, drc = ri.drc;
+        const int64_t q0 = r - j0;
+        const int64_t t0 = q0 - S.qa;                 // table index of q0 (entry 0 is q = S.qa)
+        cd u[K];
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const int64_t q = q0 - i;
+            const bool cell = (j >= act_lo && j <= jmax);
+            int64_t t = live ? t0 - i : 1;
+            t = t < 1 ? 1 : t;                        // cells past the range read a valid entry, then drop out
+            const cd pq = tP[t], pm = tP[t - 1], pp = tP[t + 1];
+            const cd et = tE[t];
+            cd v = zero();
+            cmac(v, cA, up[i]);
+            cmac(v, cB, up[i + 1]);
+            cmac(v, ga, pq + pm);
+            cmac(v, gb, pp + pq);
+            cmac(v, hp, et);
+            cmac(v, drc, pq);
+            // bar(D-j, q): the mirror pair, from the window inside the block
+            // (the window is always read, at a valid entry, so that only values are selected)
+            const bool inwin = use_win && cell && q >= W.row0;
+            const int64_t wr = inwin ? q - W.row0 : 0;
+            const int64_t wc = inwin ? D - j - W.lo : 0;
+            const cd w0 = W.w[wr][wc], w1 = W.w[wr][wc + 1];
+            cd m0 = inwin ? ((j < D) ? w0 : zero()) : mA[i];
+            const cd m1 = inwin ? w1 : mB[i];
+            if (j == D) m0 = pq * et;                 // psi(0, q)
+            cmac(v, c4, (q >= 0) ? m0 + m1 : zero());
+            u[i] = cell ? v : zero();
+        }
+        cmac(u[1], al, u[0]);
+        cmac(u[2], al, u[1]);
+        // carries: the first thread of an exact segment takes psi(0, r)
+        cd x = u[K - 1];
+        if (first && S.exact) cmac(x, a3, ri.psi0);
+        x = wave_scan(x, pw, lane, nst);
+        if (lane == 63) wave_tot[par][wv] = x;
+        const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
+        __syncthreads();
+        cd cin = prevx;
+        if (wv > S.w0) cmac(cin, lp, wave_tot[par][wv - 1]);
+        if (first) cin = S.exact ? ri.psi0 : zero();
+        // outputs
+        cd* rowp = b.ring + (int64_t)uni((int)ri.slot) * C;
+        double pe = 0.0;
+        int64_t sd = sdr;
+        sdr = inc_slot(sdr, R);
+        up[0] = cin;
+        const cd ap[K] = {a1, a2, a3};
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t j = j0 + i;
+            const bool act = (j >= act_lo && j <= jmax);
+            cd v = u[i];
+            cmac(v, ap[i], cin);
+            v = act ? v : zero();
+            up[i + 1] = v;
+            if (act && j >= S.own_lo) {
+                if (S.write_ring) rowp[j] = v;
+                if (S.write_md) b.Md[sd * Mc + j] = v;
+                pe += norm2(v);
+            }
+            if (S.write_win && act && j >= W.lo) W.w[r - W.row0][j - W.lo] = v;
+            sd = dec_slot(sd, R);
+        }
+        pe = wave_sum63(pe);
+        if (lane == 63) pe_lds[tau][wv] = pe;
+        if (use_win) __syncthreads();                 // window rows written above are read by the next row
+    };
+
+    for (int64_t r = ra; r <= rb; r += 2) {
+        step(r, MA0, MB0, MA1, MB1);
+        if (r + 1 <= rb) step(r + 1, MA1, MB1, MA0, MB0);
+    }
+}
+
 // the block's base row (row r0-1), the delay rows and mirror values of its first row
 __device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Seg& S, Lane& L, int64_t r0,
                                           const RowInfo& ri0)
@@ -677,10 +983,25 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         ri.g8r = ri.delay_on ? (0.125 * g.Gamma) * g.cinv : zero();
         ri.krc = g.cinv * ((-0.5 * g.Gamma) * (ri.half_pr - ri.half_qr));
         ri.drc = g.cinv * ri.drv;
+        ri.ga = ri.g8r * et_at(b, r - 1 - D);
+        ri.gb = ri.g8r * et_at(b, r - D);
+        ri.hp = g.cinv * ((-0.5 * g.Gamma) * ri.half_pr);
+        ri.psi0 = phi_at(b, r) * et_at(b, r);
         rinfo[threadIdx.x] = ri;
     }
     fill_pow(g.alpha, pw);
-    if (cone) {
+    if (is_strip) {
+        // strip tables reach one entry beyond each end (Phi[q-1], Phi[q+1])
+        S.qa -= 1;
+        if (cone) {
+            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab[0], tab[1], nullptr, 0, NT / 2);
+        } else {
+            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab[0], tab[1], nullptr, 0, NT);
+        }
+        if (cone)
+            fill_tables(b, D, 0, ra - D - 1, P.cone_L0 + (rb - ra) + 2, tab[0] + TBL / 2, tab[1] + TBL / 2, nullptr,
+                        NT / 2, NT / 2);
+    } else if (cone) {
         fill_tables(b, D, 0, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab[0], tab[1], nullptr, 0, NT / 2);
         fill_tables(b, D, 0, ra - D, P.cone_L0 + (rb - ra), tab[0] + TBL / 2, tab[1] + TBL / 2, nullptr, NT / 2,
                     NT / 2);
@@ -696,7 +1017,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.row0 = ra;
 
     if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
-    else march_rows<false>(g, b, W, pw, S, wave_tot, rinfo, pe_lds, ra, rb, H1, P.T, cone, use_win, P.nst);
+    else if (is_strip) strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst);
+    else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
