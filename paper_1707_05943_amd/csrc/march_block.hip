@@ -430,15 +430,19 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     auto ring_row = [&](int64_t sl) -> const char* {
         return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
     };
+    // (rows before t = 0 are zero, a uniform branch; lanes past the range
+    // read a valid entry, which only feeds dropped cells: no value selects,
+    // so the loads stay in flight until the values are used)
+    const unsigned dly_ok = live ? dly : 16u;
     auto load4 = [&](cd (&dst)[K + 1], int64_t sl) {
-        if (uni((int)sl) < 0 || !live) {
+        if (uni((int)sl) < 0) {
             #pragma unroll
             for (int i = 0; i <= K; ++i) dst[i] = zero();
-            return;
+        } else {
+            const char* rp = ring_row(sl) + dly_ok;
+            #pragma unroll
+            for (int i = 0; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
         }
-        const char* rp = ring_row(sl) + dly;
-        #pragma unroll
-        for (int i = 0; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
     };
 
     // the base row ra-1 (own columns and the one to the left) and the delay
@@ -452,16 +456,19 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
             up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
         }
     }
-    cd X[K + 1], Y[K + 1], Z[K + 1];
+    // delay rows two ahead: at row r the buffers hold rows r-D-1, r-D and
+    // r+1-D (in flight), and row r+2-D is requested
+    cd X[K + 1], Y[K + 1], Z[K + 1], V[K + 1];
     load4(X, slot_or_neg(ra - 1 - D, g.R));
     load4(Y, slot_or_neg(ra - D, g.R));
+    if (ra + 1 <= rb) load4(Z, rinfo[0].slot_pf);
 
     auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        if (r + 1 <= rb) load4(N, ri.slot_pf);
+        if (r + 2 <= rb) load4(N, rinfo[tau + 1].slot_pf);
         // beta of the three columns
         cd p[K + 1];
         #pragma unroll
@@ -513,10 +520,11 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (lane == 63) pe_lds[tau][wv] = pe;
     };
 
-    for (int64_t r = ra; r <= rb; r += 3) {
-        step(r, X, Y, Z);
+    for (int64_t r = ra; r <= rb; r += 4) {
+        step(r, X, Y, V);
         if (r + 1 <= rb) step(r + 1, Y, Z, X);
-        if (r + 2 <= rb) step(r + 2, Z, X, Y);
+        if (r + 2 <= rb) step(r + 2, Z, V, Y);
+        if (r + 3 <= rb) step(r + 3, V, X, Z);
     }
 }
 
@@ -550,29 +558,37 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
     };
     // delay row rho (ring slot sl; sl < 0 before t = 0)
+    const unsigned dly_ok = live ? dly : 16u;
     auto load4 = [&](cd (&dst)[K + 1], int64_t sl, int64_t rho) {
-        const int s32 = uni((int)sl);
-        const bool ok = s32 >= 0 && live;
-        const char* rp = ring_row(s32 < 0 ? 0 : s32) + dly;
-        cd v[K + 1];
-        #pragma unroll
-        for (int i = 0; i <= K; ++i) v[i] = ok ? *reinterpret_cast<const cd*>(rp + 16 * i) : zero();
-        cd e0 = zero();
-        if (ok && dcol == 0) e0 = b.Phi[rho] * b.Et[rho];
-        dst[0] = (dcol == 0) ? e0 : v[0];
-        #pragma unroll
-        for (int i = 1; i <= K; ++i) dst[i] = v[i];
+        if (uni((int)sl) < 0) {
+            #pragma unroll
+            for (int i = 0; i <= K; ++i) dst[i] = zero();
+        } else {
+            const char* rp = ring_row(sl) + dly_ok;
+            #pragma unroll
+            for (int i = 1; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
+            // column 0 (the region's first column only) is the exact solution
+            if (dcol == 0) dst[0] = b.Phi[rho] * b.Et[rho];
+            else dst[0] = *reinterpret_cast<const cd*>(rp);
+        }
     };
-    // mirror pair of row r for the cells with j < 2D (j = 2D: only the second)
-    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB) {
+    // mirror pair of row rr for the cells with j <= 2D: psi(2D-j, q+D) and
+    // psi(2D-j+1, q+D), q = rr - j; at j = 2D the first is exact and Phi[q+D]
+    // is loaded (its Et[q+D] factor is applied where it is used).  One load per
+    // value from a chosen address, so the values are not waited for here;
+    // cells without a mirror read a valid entry and are dropped where used.
+    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB, int64_t rr) {
         const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
         const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t c = 2 * D - (j0 + i);
             const bool ok = live && j0 + i <= jmax && c >= 0;
-            mA[i] = (ok && c >= 1) ? rA[c] : zero();
-            mB[i] = ok ? rB[c + 1] : zero();
+            const int64_t qd = rr - (j0 + i) + D;
+            const cd* pa = !ok ? rA + 1 : (c >= 1 ? rA + c : b.Phi + (qd >= 0 ? qd : 0));
+            const cd* pb = ok ? rB + c + 1 : rB + 1;
+            mA[i] = *pa;
+            mB[i] = *pb;
         }
     };
 
@@ -589,17 +605,24 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     load4(X, slot_or_neg(ra - 1 - D, g.R), ra - 1 - D);
     load4(Y, slot_or_neg(ra - D, g.R), ra - D);
     cd mA[K], mB[K], nA[K], nB[K];
-    load_m(mA, mB, rinfo[0].slot, rinfo[0].slot_m1);
+    load_m(mA, mB, rinfo[0].slot, rinfo[0].slot_m1, ra);
+    // the exact segment's carry psi(lo-1, r) (written by the strip a launch
+    // earlier), a row ahead
+    const unsigned cofs = (unsigned)((S.lo - 1) * 16);
+    cd cnext = zero();
+    if (first && S.exact) cnext = *reinterpret_cast<const cd*>(ring_row(rinfo[0].slot) + cofs);
 
     auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
+        const cd carry0 = cnext;
         if (r + 1 <= rb) {
             load4(N, ri.slot_pf, r + 1 - D);
             const RowInfo& rn = rinfo[tau + 1];
-            load_m(nA, nB, rn.slot, rn.slot_m1);
+            load_m(nA, nB, rn.slot, rn.slot_m1, r + 1);
+            if (first && S.exact) cnext = *reinterpret_cast<const cd*>(ring_row(rn.slot) + cofs);
         }
         cd p[K + 1];
         #pragma unroll
@@ -622,9 +645,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             cmac(v, drc, ph);
             if (j <= 2 * D) {
                 // second source: -(G/2)[ (m0 + m1)/2 - Et[q+D] half_pr ]
-                cd ph2 = zero();
-                if (j == 2 * D && q + D >= 0) ph2 = b.Phi[q + D];
-                const cd m0 = (j == 2 * D) ? ph2 * et2 : mA[i];
+                const cd m0 = (j == 2 * D) ? mA[i] * et2 : mA[i];
                 cmac(v, -c4, (q + D >= 0) ? m0 + mB[i] : zero());
                 cmac(v, -hp, et2);
             } else {
@@ -635,18 +656,14 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         cmac(u[1], al, u[0]);
         cmac(u[2], al, u[1]);
         cd x = u[K - 1];
-        cd carry0 = zero();
-        if (first && S.exact) {
-            carry0 = *reinterpret_cast<const cd*>(ring_row(ri.slot) + (unsigned)((S.lo - 1) * 16));
-            cmac(x, a3, carry0);
-        }
+        if (first && S.exact) cmac(x, a3, carry0);
         x = wave_scan(x, pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
         __syncthreads();
         cd cin = prevx;
         if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
-        if (first) cin = carry0;
+        if (first) cin = S.exact ? carry0 : zero();
         char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
         double pe = 0.0;
         up[0] = cin;
@@ -708,6 +725,8 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
 
     // mirror values of row r for this thread's cells: diagonals r-D (Md row
     // slot(r)) at column D-j, and r-D-1 (slot(r-1)) at column D-j+1
+    // (one load per value from a valid address, no selects: cells without a
+    // mirror read are dropped, or replaced, where the values are used)
     auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB) {
         const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
         const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
@@ -715,8 +734,8 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         for (int i = 0; i < K; ++i) {
             const int64_t c = D - (j0 + i);
             const bool ok = live && j0 + i <= jmax;
-            mA[i] = (ok && c >= 1) ? rA[c] : zero();
-            mB[i] = ok ? rB[c + 1] : zero();
+            mA[i] = rA[(ok && c >= 1) ? c : 1];
+            mB[i] = rB[ok ? c + 1 : 1];
         }
     };
 
