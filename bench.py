@@ -197,19 +197,34 @@ def run_sweep(n_train: int, n_pts: int, steps: int, tol: float = 1e-3) -> dict:
     log = lambda m: print(m, file=sys.stderr, flush=True)
     solver = SW.Solver()
     t0 = time.perf_counter()
-    x, t, m = SW.make_dataset(W.sweep_draw(n_train, 101), solver, chunk=512)
+    train_set = W.sweep_draw(n_train, 101)
+    x, t, m = SW.make_dataset(train_set, solver, chunk=512)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     net = SW.train(x, t, m, steps=steps, batch=32, lr=1e-3, log=log)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # the corrector: the same network shape on (encoding, coarse P_e) -> P_fine - P_coarse
+    xc, tc, mc, cscale = SW.make_corrector_dataset(train_set, solver, fine=t[:, :, 0], log=log)
     del x, t, m
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    cnet = SW.train(xc, tc, mc, steps=steps, batch=32, lr=1e-3, log=log, weights=(1.0,), seed=6)
+    cnet.corr_scale = cscale
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    del xc, tc, mc
     pts = W.sweep_draw(n_pts, 202)
     ta = time.perf_counter()
     plain = torch.cat([solver.solve(pts[s:s + 512], with_chi=False)[0] for s in range(0, n_pts, 512)])
     torch.cuda.synchronize()
     tb = time.perf_counter()
     out, ok, info = SW.sweep(pts, net, solver, tol=tol, log=log)
+    cout, cok, cinfo, rich = SW.sweep_corrected(pts, cnet, solver, tol=tol, log=log)
+    cerr = SW.rel_err(cout, plain).cpu().numpy()
+    cacc = cok.cpu().numpy()
+    rvalid = ~torch.isnan(rich[:, 0])
+    rerr = SW.rel_err(rich[rvalid], plain[rvalid]).cpu().numpy()
     err = SW.rel_err(out, plain)
     s_err = SW.rel_err(SW.predict_pe(net, SW.features(pts, solver.device)), plain)
     acc = ok.cpu().numpy()
@@ -247,6 +262,15 @@ def run_sweep(n_train: int, n_pts: int, steps: int, tol: float = 1e-3) -> dict:
             "surrogate_alone_p90_rel_err": float(np.quantile(s_err.cpu().numpy(), 0.9)),
             "timing_s": {k: info[k] for k in ("surrogate_s", "check_s", "fallback_s", "total_s")},
             "inference_points_per_s": len(big) / t_inf,
+            "corrected": {"points_per_s": n_pts / cinfo["total_s"], "accepted": int(cacc.sum()),
+                          "fallback": cinfo["fallback"],
+                          "accepted_true_err_above_tol": int(((cerr > tol) & cacc).sum()),
+                          "max_true_err": float(cerr.max()), "median_true_err": float(np.median(cerr)),
+                          "timing_s": {k: cinfo[k] for k in ("coarse_s", "network_s", "fallback_s", "total_s")},
+                          "richardson_only": {"points": int(rerr.size),
+                                              "frac_within_tol": float((rerr <= tol).mean()) if rerr.size else 0.0,
+                                              "median_rel_err": float(np.median(rerr)) if rerr.size else None},
+                          "train_s": t4 - t3},
             "plain_on_coarser_grid": coarse,
             "training": {"instances": n_train, "data_s": t1 - t0, "steps": steps, "train_s": t2 - t1,
                          "ms_per_step": (t2 - t1) / steps * 1e3, "batch": 32}}

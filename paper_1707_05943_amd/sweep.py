@@ -172,20 +172,21 @@ def make_dataset(insts, solver: Solver, chunk=512, log=None):
 LOSS_WEIGHTS = (4.0, 1.0, 1.0)
 
 
-def surrogate_cfg(max_batch=32):
-    return S.cfg(n_points=N_SAMPLES, c_in=C_IN, width=64, modes=64, layers=4, proj=128, c_out=C_OUT,
+def surrogate_cfg(max_batch=32, c_in=C_IN, c_out=C_OUT):
+    return S.cfg(n_points=N_SAMPLES, c_in=c_in, width=64, modes=64, layers=4, proj=128, c_out=c_out,
                  max_batch=max_batch)
 
 
-def train(x, t, m, steps=2000, batch=32, lr=1e-3, seed=5, net=None, log=None):
-    """Adam on random mini-batches of (x, t, m); returns the network"""
+def train(x, t, m, steps=2000, batch=32, lr=1e-3, seed=5, net=None, log=None, weights=LOSS_WEIGHTS):
+    """Adam on random mini-batches of (x, t, m); returns the network (its
+    input and output channels are those of x and t)"""
     import torch
     dev = x.device
     if net is None:
-        c = surrogate_cfg(batch)
+        c = surrogate_cfg(batch, c_in=x.shape[2], c_out=t.shape[2])
         theta = SI.init_params(SI.cfg_dict(c), seed)
         net = S.Net(c, torch.from_numpy(theta).to(dev), device=str(dev))
-    wo = torch.tensor(LOSS_WEIGHTS, dtype=torch.float32, device=dev)
+    wo = torch.tensor(weights, dtype=torch.float32, device=dev)
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
     n = x.shape[0]
@@ -258,3 +259,97 @@ def sweep(insts, net, solver: Solver, tol=1e-3, accept=None, factor=4, chunk=512
             f"fallback {len(fb)} points {t3 - t2:.2f} s")
     return out, ok, {"surrogate_s": t1 - t0, "check_s": t2 - t1, "fallback_s": t3 - t2, "total_s": t3 - t0,
                      "fallback": len(fb), "points": len(insts)}
+
+
+# ---------------------------------------------------------------------------
+# Corrected sweep: a network predicts the difference between the fine solve's
+# P_e and that of a 4x coarser FP64 solve; the a-posteriori check compares the
+# prediction with the Richardson estimate of the same difference from a
+# second, 8x coarser solve (the scheme is second order:
+# P_h = P + K h^2, so P_fine - P_4 = (P_8 - P_4)(Delta^2 - h_4^2)/(h_8^2 - h_4^2)).
+# ---------------------------------------------------------------------------
+CORR_SCALE = 100.0          # default scale of the difference seen by the network (set from the data)
+
+
+def coarse_pe(insts, solver: Solver, factor: int, chunk=512):
+    """P_e of each point on its `factor`-coarser grid, sampled on the point's
+    own window; (pe (B, n), valid (B,) bool, grid steps (B,))"""
+    import torch
+    dev = solver.device
+    cs = [coarse(i, factor) for i in insts]
+    have = [i for i, c in enumerate(cs) if c is not None]
+    pe = torch.zeros(len(insts), N_SAMPLES, dtype=torch.float64, device=dev)
+    for s in range(0, len(have), chunk):
+        ids = have[s:s + chunk]
+        p, _, _ = solver.solve([cs[i] for i in ids], with_chi=False, t_end=[pe_window(insts[i]) for i in ids])
+        pe[torch.tensor(ids, device=dev)] = p
+    valid = torch.zeros(len(insts), dtype=torch.bool, device=dev)
+    if have:
+        valid[torch.tensor(have, device=dev)] = True
+    h = torch.tensor([c.Delta if c is not None else float("nan") for c in cs], dtype=torch.float64, device=dev)
+    return pe, valid, h
+
+
+def corrector_inputs(insts, c4, device):
+    """the surrogate's encoding plus the coarse solve's P_e as a ninth channel"""
+    import torch
+    return torch.cat([features(insts, device), c4.to(torch.float32)[:, :, None]], dim=2).contiguous()
+
+
+def make_corrector_dataset(insts, solver: Solver, chunk=512, log=None, fine=None):
+    """inputs and targets (P_fine - P_4) x CORR_SCALE of the points whose
+    coarse grid is valid (`fine`: the points' fine P_e samples, if at hand)"""
+    import torch
+    if fine is None:
+        fine = torch.cat([solver.solve(insts[s:s + chunk], with_chi=False)[0] for s in range(0, len(insts), chunk)])
+    fine = fine.to(torch.float64)
+    c4, v4, _ = coarse_pe(insts, solver, 4, chunk)
+    keep = [i for i, v in enumerate(v4.tolist()) if v]
+    idx = torch.tensor(keep, device=solver.device)
+    x = corrector_inputs([insts[i] for i in keep], c4[idx], solver.device)
+    d = fine[idx] - c4[idx]
+    scale = 1.0 / max(float(torch.sqrt(torch.mean(d * d))), 1e-300)     # unit RMS targets
+    t = (d * scale).to(torch.float32)[:, :, None].contiguous()
+    m = torch.ones_like(t)
+    if log:
+        log(f"[sweep] corrector data: {len(keep)} of {len(insts)} points have a coarse grid, "
+            f"difference RMS {1.0 / scale:.3e}")
+    return x, t, m, scale
+
+
+def sweep_corrected(insts, net, solver: Solver, tol=1e-3, accept=None, chunk=512, log=None):
+    """P_e of every point: coarse solve + network correction where the check
+    passes (the two estimates of the correction agree within tol/4 relative),
+    the fine FP64 solve elsewhere.  Returns (P_e, accepted, info,
+    Richardson-only estimate)."""
+    import torch
+    accept = tol / 4 if accept is None else accept
+    dev = solver.device
+    t0 = time.perf_counter()
+    c4, v4, h4 = coarse_pe(insts, solver, 4, chunk)
+    c8, v8, h8 = coarse_pe(insts, solver, 8, chunk)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x = corrector_inputs(insts, c4, dev)
+    d_nn = predict_pe(net, x) / getattr(net, "corr_scale", CORR_SCALE)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    hf = torch.tensor([i.Delta for i in insts], dtype=torch.float64, device=dev)
+    w = ((hf ** 2 - h4 ** 2) / (h8 ** 2 - h4 ** 2))[:, None]
+    d_r = (c8 - c4) * w
+    scale = torch.clamp(torch.linalg.norm(c4, dim=1), min=1e-300)
+    ok = v4 & v8 & (torch.linalg.norm(d_nn - d_r, dim=1) / scale <= accept)
+    out = c4 + d_nn
+    rich = torch.where((v4 & v8)[:, None], c4 + d_r, torch.full_like(c4, float("nan")))
+    fb = [i for i, a in enumerate(ok.tolist()) if not a]
+    for s in range(0, len(fb), chunk):
+        ids = fb[s:s + chunk]
+        pe, _, _ = solver.solve([insts[i] for i in ids], with_chi=False)
+        out[torch.tensor(ids, device=dev)] = pe
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    if log:
+        log(f"[sweep] corrected, {len(insts)} points: coarse solves {t1 - t0:.2f} s, network {t2 - t1:.2f} s, "
+            f"fallback {len(fb)} points {t3 - t2:.2f} s")
+    return out, ok, {"coarse_s": t1 - t0, "network_s": t2 - t1, "fallback_s": t3 - t2, "total_s": t3 - t0,
+                     "fallback": len(fb), "points": len(insts)}, rich

@@ -98,3 +98,32 @@ def test_sweep_fallback_logic(trained, solver):
     pred = SW.predict_pe(net, SW.features(pts, solver.device))
     sel = torch.tensor(have, device=out.device)
     assert torch.equal(out[sel], pred[sel]) and torch.equal(out[~sel], plain[~sel])
+
+
+def test_corrected_sweep_logic(solver):
+    """the corrector network on a small training set: its accepted points are
+    coarse + correction, the others the fine solve bitwise; the errors of the
+    coarse solve, the corrected one and the Richardson estimate are reported"""
+    import torch
+    train_set = _small_draw(128, 45)
+    xc, tc, mc, cscale = SW.make_corrector_dataset(train_set, solver, log=_say)
+    cnet = SW.train(xc, tc, mc, steps=600, batch=32, lr=1e-3, log=_say, weights=(1.0,), seed=6)
+    cnet.corr_scale = cscale
+    pts = _small_draw(24, 46)
+    plain, _, _ = solver.solve(pts, with_chi=False)
+    out, ok, info, rich = SW.sweep_corrected(pts, cnet, solver, tol=1e-3, log=_say)
+    fb = ~ok
+    assert torch.equal(out[fb], plain[fb])
+    c4, v4, _ = SW.coarse_pe(pts, solver, 4)
+    pred = SW.predict_pe(cnet, SW.corrector_inputs(pts, c4, solver.device)) / cscale
+    if bool(ok.any()):
+        assert torch.equal(out[ok], (c4 + pred)[ok])
+    e_c = SW.rel_err(c4[v4], plain[v4])
+    e_n = SW.rel_err((c4 + pred)[v4], plain[v4])
+    rv = ~torch.isnan(rich[:, 0])
+    e_r = SW.rel_err(rich[rv], plain[rv])
+    _say(f"[sweep] median rel-L2 of P_e: coarse {e_c.median():.2e}, coarse + network {e_n.median():.2e}, "
+         f"coarse + Richardson {e_r.median():.2e}; accepted {int(ok.sum())}/{len(pts)}")
+    # accepted points meet the tolerance the check was set for
+    e_out = SW.rel_err(out, plain)
+    assert float(e_out[ok].max()) <= 1e-3 if bool(ok.any()) else True
