@@ -421,7 +421,9 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     const unsigned own = (unsigned)(j0 * 16);                 // byte offset of column j0 in a row
     const unsigned dly = (unsigned)((j0 - 1 - D) * 16);       // ... of column j0-1-D (>= 1: j0 > 2D)
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
-    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    cd ap[K];                                                 // alpha^(i+1)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
     const cd lp = pw.lp[lane];
     const cd* tE = S.tE;
     const cd* tP = S.tP;
@@ -488,8 +490,8 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
             cmac(v, drc, tP[t]);
             u[i] = (j >= act_lo && j <= jmax) ? v : zero();
         }
-        cmac(u[1], al, u[0]);
-        cmac(u[2], al, u[1]);
+        #pragma unroll
+        for (int i = 1; i < K; ++i) cmac(u[i], al, u[i - 1]);
         // carries across threads and waves
         cd x = wave_scan(u[K - 1], pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
@@ -501,7 +503,6 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
         double pe = 0.0;
         up[0] = cin;
-        const cd ap[K] = {a1, a2, a3};
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t j = j0 + i;
@@ -547,7 +548,9 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     const unsigned own = (unsigned)(j0 * 16);
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
-    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    cd ap[K];                                                 // alpha^(i+1)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
     const cd lp = pw.lp[lane];
     const cd* tE = S.tE;
     const cd* tP = S.tP;
@@ -653,10 +656,10 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             }
             u[i] = cell ? v : zero();
         }
-        cmac(u[1], al, u[0]);
-        cmac(u[2], al, u[1]);
+        #pragma unroll
+        for (int i = 1; i < K; ++i) cmac(u[i], al, u[i - 1]);
         cd x = u[K - 1];
-        if (first && S.exact) cmac(x, a3, carry0);
+        if (first && S.exact) cmac(x, ap[K - 1], carry0);
         x = wave_scan(x, pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
@@ -667,7 +670,6 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
         double pe = 0.0;
         up[0] = cin;
-        const cd ap[K] = {a1, a2, a3};
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t j = j0 + i;
@@ -717,7 +719,9 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const bool live = j0 <= jmax;
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
-    const cd a1 = pw.a[1], a2 = pw.a[2], a3 = pw.a[3];
+    cd ap[K];                                                 // alpha^(i+1)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
     const cd lp = pw.lp[lane];
     const cd* tE = S.tE;
     const cd* tP = S.tP;
@@ -795,11 +799,11 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             cmac(v, c4, (q >= 0) ? m0 + m1 : zero());
             u[i] = cell ? v : zero();
         }
-        cmac(u[1], al, u[0]);
-        cmac(u[2], al, u[1]);
+        #pragma unroll
+        for (int i = 1; i < K; ++i) cmac(u[i], al, u[i - 1]);
         // carries: the first thread of an exact segment takes psi(0, r)
         cd x = u[K - 1];
-        if (first && S.exact) cmac(x, a3, ri.psi0);
+        if (first && S.exact) cmac(x, ap[K - 1], ri.psi0);
         x = wave_scan(x, pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
@@ -813,7 +817,6 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         int64_t sd = sdr;
         sdr = inc_slot(sdr, R);
         up[0] = cin;
-        const cd ap[K] = {a1, a2, a3};
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t j = j0 + i;
