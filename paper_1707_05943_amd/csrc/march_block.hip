@@ -39,6 +39,10 @@
 //    second half of threads in the same row pass;
 //  * all other mirror reads come from a copy of the strip stored along
 //    anti-diagonals, so that the reads of one row are contiguous.
+// Each workgroup runs the row loop of its region -- the strip (its delay
+// corners are exact), the near outgoing region D < j <= 2D + halo (delay
+// from the ring, second source mirrored), or the far region (every source
+// exact) -- with the region's terms and no per-cell branching on the region.
 // The kernel boundary between launches makes every write of a launch
 // visible to the next one; no flags or fences are needed.
 
@@ -60,15 +64,6 @@ __device__ inline int64_t slot_or_neg(int64_t rho, int64_t R) { return rho < 0 ?
 
 __device__ inline cd phi_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Phi[q] : zero(); }
 __device__ inline cd et_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Et[q] : zero(); }
-
-// psi at column i, row rho from memory: zero before t = 0, the exact solution
-// at columns <= 0, the ring otherwise
-__device__ inline cd rd(const Geom& g, const Bufs& b, int64_t i, int64_t rho)
-{
-    if (rho < 0) return zero();
-    if (i <= 0) return b.Phi[rho - i] * b.Et[rho];
-    return b.ring[(rho % g.R) * g.C + i];
-}
 
 // cross-lane moves with DPP (GFX9 encodings); lanes without a source get 0
 // (bound_ctrl), every row is written: the row-broadcast stages' multipliers
@@ -197,200 +192,6 @@ struct Seg {
     const cd* tP;                // Phi[q]
     const cd* tE2;               // Et[q+D] (near columns)
 };
-
-// Per-thread state through a block.
-struct Lane {
-    cd up[K + 1];                // psi(j0-1+i, r-1): the left neighbour, then the thread's columns
-    cd dA[K + 1];                // row r-1-D at columns j0-1-D .. j0+K-1-D
-    cd dB[K + 1];                // row r-D at the same columns
-    cd mA[K], mB[K];             // mirror values of this row: diagonals r-D and r-D-1
-    int64_t sd;                  // row of Md holding diagonal r - j0 (the thread's first column)
-};
-
-// delay values of row rho (ring slot `sl`, or sl < 0 before t = 0)
-__device__ __forceinline__ void load_delay_row(const Geom& g, const Bufs& b, int64_t j0, int64_t rho, int64_t sl,
-                                               cd* out)
-{
-    if (sl < 0) {
-        #pragma unroll
-        for (int i = 0; i <= K; ++i) out[i] = zero();
-        return;
-    }
-    const cd* row = b.ring + sl * g.C;
-    #pragma unroll
-    for (int i = 0; i <= K; ++i) {
-        const int64_t c = j0 - 1 - g.D + i;
-        out[i] = (c <= 0) ? b.Phi[rho - c] * b.Et[rho] : ((c <= g.Nx) ? row[c] : zero());
-    }
-}
-
-// mirror values needed by columns j0.. at the row whose diagonals r-D and
-// r-D-1 sit in Md rows sA and sB: psi(D-j, r-j), psi(D-j+1, r-j) for strip
-// columns, psi(2D-j, r-j+D), psi(2D-j+1, r-j+D) for near columns (column 0
-// entries are left to the exact solution)
-__device__ __forceinline__ void load_mirror(const Geom& g, const Bufs& b, int64_t j0, int64_t sA, int64_t sB,
-                                            cd* mA, cd* mB)
-{
-    const int64_t D = g.D;
-    const cd* rowA = b.Md + sA * g.Mc;
-    const cd* rowB = b.Md + sB * g.Mc;
-    #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int64_t j = j0 + i;
-        int64_t c = -1;
-        if (j >= 1 && j <= D) c = D - j;
-        else if (j > D && j <= 2 * D) c = 2 * D - j;
-        mA[i] = (c >= 1) ? rowA[c] : zero();
-        mB[i] = (c >= 0) ? rowB[c + 1] : zero();
-    }
-}
-
-// One row of one thread's segment.  FAR: every column of the range lies
-// beyond 2D, where all source terms are exact (tables dE and Phi).
-// Returns this thread's share of sum |psi|^2 over the owned columns.
-template <bool FAR>
-__device__ __forceinline__ double do_row(const Geom& g, const Bufs& b, const Win& W, const Pow& P, const Seg& S,
-                                         Lane& L, cd (*wave_tot)[NW], const RowInfo& ri, const RowInfo* rnext,
-                                         int64_t r, int64_t rb, int64_t act_lo, int par, int nst)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int64_t j0 = S.lo + (int64_t)(tid - S.t0) * K;
-    const int64_t D = g.D;
-    const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
-    const int any = (j0 + K - 1 >= act_lo) && (j0 <= jmax);
-    const double g8 = 0.125 * g.Gamma, g2 = 0.5 * g.Gamma;
-
-    // prefetch the delay row (and the mirror values) of the next row
-    cd nx[K + 1];
-    cd nA[K], nB[K];
-    const int pf = any && r + 1 <= rb;
-    if (pf) {
-        load_delay_row(g, b, j0, r + 1 - D, ri.slot_pf, nx);
-        if (!FAR) load_mirror(g, b, j0, rnext->slot, rnext->slot_m1, nA, nB);
-    }
-
-    cd u[K];
-    if (any) {
-        if (FAR) {
-            const cd kr = (-g2) * (ri.half_pr - ri.half_qr);
-            #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int64_t j = j0 + i;
-                cd Sv = zero();
-                if (ri.delay_on) Sv = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
-                const int64_t t = r - j - S.qa;
-                Sv += kr * S.tE[t] + ri.drv * S.tP[t];
-                const cd v = g.cA * L.up[i] + g.cB * L.up[i + 1] + g.cinv * Sv;
-                u[i] = (j >= act_lo && j <= jmax) ? v : zero();
-            }
-        } else {
-            #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int64_t j = j0 + i;
-                cd Sv = zero();
-                if (ri.delay_on) Sv = g8 * ((L.dA[i] + L.dA[i + 1]) + (L.dB[i] + L.dB[i + 1]));
-                cd src = zero();
-                const int64_t q = r - j;
-                const int64_t t = q - S.qa;
-                const int ok = (j >= act_lo && j <= jmax);
-                if (ok && q >= 0) {
-                    const cd et = S.tE[t];
-                    const cd ph = S.tP[t];
-                    cd mir;
-                    if (j <= D) {
-                        // bar(D-j, r-j): psi(D-j, q) on diagonal r-D, psi(D-j+1, q) on r-D-1
-                        const int inwin = S.use_win && q >= W.row0;
-                        const int64_t wr = inwin ? q - W.row0 : 0;
-                        const int64_t wc = inwin ? D - j - W.lo : 0;
-                        const cd w0 = inwin && j < D ? W.w[wr][wc] : zero();
-                        const cd w1 = inwin ? W.w[wr][wc + 1] : zero();
-                        const cd m0 = (j == D) ? ph * et : (inwin ? w0 : L.mA[i]);
-                        const cd m1 = inwin ? w1 : L.mB[i];
-                        mir = 0.5 * (m0 + m1);
-                    } else {
-                        mir = et * ri.half_qr;
-                    }
-                    src = et * ri.half_pr - mir;
-                    Sv += ri.drv * ph;
-                }
-                if (ok && j > D && q + D >= 0) {
-                    const cd et2 = S.tE2[t];
-                    cd mir2;
-                    if (j <= 2 * D) {
-                        // bar(2D-j, r-j+D): diagonals r-D and r-D-1 again
-                        const cd m0 = (j == 2 * D) ? b.Phi[q + D] * et2 : L.mA[i];
-                        mir2 = 0.5 * (m0 + L.mB[i]);
-                    } else {
-                        mir2 = et2 * ri.half_qr;
-                    }
-                    src += mir2 - et2 * ri.half_pr;
-                }
-                Sv -= g2 * src;
-                const cd v = g.cA * L.up[i] + g.cB * L.up[i + 1] + g.cinv * Sv;
-                u[i] = ok ? v : zero();
-            }
-        }
-        #pragma unroll
-        for (int i = 1; i < K; ++i) u[i] = g.alpha * u[i - 1] + u[i];
-    } else {
-        #pragma unroll
-        for (int i = 0; i < K; ++i) u[i] = zero();
-    }
-
-    // carry into the segment
-    cd carry0 = zero();
-    if (S.exact && tid == S.t0) {
-        const int64_t c = S.lo - 1;
-        carry0 = (c <= 0) ? b.Phi[r - c] * b.Et[r] : b.ring[ri.slot * g.C + c];
-    }
-
-    // x_t = u_last + alpha^K x_{t-1}: inclusive scan over the segment's threads
-    cd x = u[K - 1];
-    if (tid == S.t0) x += P.a[K] * carry0;
-    x = wave_scan(x, P, lane, nst);
-    if (lane == 63) wave_tot[par][wv] = x;
-    const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
-    __syncthreads();
-    // the previous wave's last lane; waves further left enter with at least
-    // alpha^(64 K), below 2^-60 relative for every admissible alpha
-    const cd wcarry = (wv > S.w0) ? wave_tot[par][wv - 1] : zero();
-    // the value just left of this thread's first column
-    cd cin = prevx + P.lp[lane] * wcarry;
-    if (tid == S.t0) cin = carry0;
-
-    double pe = 0.0;
-    if (any) {
-        cd* row = b.ring + ri.slot * g.C;
-        int64_t sd = L.sd;
-        #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int64_t j = j0 + i;
-            const int act = (j >= act_lo && j <= jmax);
-            const cd v = act ? u[i] + P.a[i + 1] * cin : zero();
-            u[i] = v;
-            if (act && j >= S.own_lo) {
-                if (S.write_ring) row[j] = v;
-                if (S.write_md) b.Md[sd * g.Mc + j] = v;
-                const double m2 = norm2(v);
-                pe += (j == g.Nx) ? 0.5 * m2 : m2;
-            }
-            if (S.write_win && act && j >= W.lo && j <= D) W.w[r - W.row0][j - W.lo] = v;
-            sd = dec_slot(sd, g.R);
-        }
-        // advance: psi(j0-1, r) is the carry that entered this thread
-        L.up[0] = cin;
-        #pragma unroll
-        for (int i = 0; i < K; ++i) L.up[i + 1] = u[i];
-        #pragma unroll
-        for (int i = 0; i <= K; ++i) { L.dA[i] = L.dB[i]; L.dB[i] = nx[i]; }
-        if (!FAR && pf) {
-            #pragma unroll
-            for (int i = 0; i < K; ++i) { L.mA[i] = nA[i]; L.mB[i] = nB[i]; }
-        }
-        L.sd = inc_slot(L.sd, g.R);
-    }
-    return pe;
-}
 
 // acc += a b with four fused multiply-adds
 __device__ __forceinline__ void cmac(cd& acc, const cd a, const cd b)
@@ -844,25 +645,6 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     }
 }
 
-// the block's base row (row r0-1), the delay rows and mirror values of its first row
-__device__ __forceinline__ void load_base(const Geom& g, const Bufs& b, const Seg& S, Lane& L, int64_t r0,
-                                          const RowInfo& ri0)
-{
-    const int64_t j0 = S.lo + (int64_t)(threadIdx.x - S.t0) * K;
-    #pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const int64_t j = j0 + i;
-        L.up[i + 1] = (j <= g.Nx && j < S.hi) ? rd(g, b, j, r0 - 1) : zero();
-    }
-    L.up[0] = (j0 - 1 <= g.Nx) ? rd(g, b, j0 - 1, r0 - 1) : zero();
-    const int64_t rA = r0 - 1 - g.D, rB = r0 - g.D;
-    load_delay_row(g, b, j0, rA, slot_or_neg(rA, g.R), L.dA);
-    load_delay_row(g, b, j0, rB, slot_or_neg(rB, g.R), L.dB);
-    load_mirror(g, b, j0, ri0.slot, ri0.slot_m1, L.mA, L.mB);
-    const int64_t d = r0 - j0 + g.D;                    // diagonal r0 - j0, offset by D
-    L.sd = ((d % g.R) + g.R) % g.R;
-}
-
 // tables of q = r - j over a block for the columns lo..hi-1 and rows ra..rb
 __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64_t n, cd* tE, cd* tP, cd* tE2,
                             int t_begin, int t_count)
@@ -878,28 +660,6 @@ __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64
             tP[t] = phi_at(b, q);
             if (tE2) tE2[t] = et_at(b, q + D);
         }
-    }
-}
-
-// the rows of a block for one thread's segment
-template <bool FAR>
-__device__ __forceinline__ void march_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw, const Seg& S,
-                                           cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
-                                           int64_t ra, int64_t rb, int H1, int T, int cone, int use_win, int nst)
-{
-    Lane L;
-    load_base(g, b, S, L, ra, rinfo[0]);
-    for (int64_t r = ra; r <= rb; ++r) {
-        const int tau = (int)(r - ra);
-        const int par = tau & 1;
-        int64_t act = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        if (cone && threadIdx.x >= NT / 2 && tau > T - 2) act = S.hi;     // the cone stops a row early
-        const RowInfo ri = rinfo[tau];
-        const RowInfo* rn = &rinfo[tau + 1 < BM_TMAX ? tau + 1 : tau];
-        double pe = do_row<FAR>(g, b, W, pw, S, L, wave_tot, ri, rn, r, rb, act, par, nst);
-        pe = wave_sum63(pe);
-        if ((threadIdx.x & 63) == 63) pe_lds[tau][threadIdx.x >> 6] = pe;
-        if (use_win) __syncthreads();            // window rows written above are read by the next row
     }
 }
 
