@@ -94,7 +94,7 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
 static int validate(const fdtd_params* p, char* why, size_t n) { return ctx_validate(p, SOLO_KNOBS, why, n); }
 
 struct Layout {
-    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, total;
+    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, Epart, total;
 };
 
 // ring rows: the delay reaches D+1 rows back; the strip runs one block of T
@@ -121,6 +121,11 @@ static Layout layout(const fdtd_params* p, const Plan& P)
     L.Gn = off; off += align256((p->D + 1) * ODE_P * 16);
     L.ode = off; off += align256((int64_t)sizeof(OdeTab));
     L.odeinst = off; off += align256((int64_t)sizeof(OdeInst));
+    L.Epart = -1;
+    if (p->incident == FDTD_INC_GAUSS2 && p->boundary == FDTD_E_SERIES) {
+        L.Epart = off;
+        off += align256((int64_t)EPART_CHUNKS * n * 16);
+    }
     L.total = off;
     return L;
 }
@@ -245,6 +250,7 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     b.status = (int*)(base + L.status);
     b.Gn = (cd*)(base + L.Gn);
     b.ode = (OdeTab*)(base + L.ode);
+    b.Epart = L.Epart >= 0 ? (cd*)(base + L.Epart) : nullptr;
     c->d_ode = (OdeInst*)(base + L.odeinst);
     c->row = -1;
     c->strip_row = -1;

@@ -165,7 +165,35 @@ __global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
 
 // source of E in k_E: computed here, copied from Ebuf, or formed from the
 // delay equation's G in Ebuf
-enum { E_COMPUTE = 0, E_COPY = 1, E_FROM_G = 2 };
+enum { E_COMPUTE = 0, E_COPY = 1, E_FROM_G = 2, E_SUM_PARTS = 3 };
+
+// the Gaussian's plane-wave superposition, split over chunks of Fourier
+// nodes (blockIdx.y) so that short windows still fill the chip; the chunks'
+// partial sums are added in a fixed order by k_E
+__global__ __launch_bounds__(64) void k_E_part(Geom g, Packet pk, Bufs b, int nk, double k_lo, double hk, int chunks)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > g.Nt) return;
+    const int c = blockIdx.y;
+    const int i0 = (int)(((int64_t)nk * c) / chunks), i1 = (int)(((int64_t)nk * (c + 1)) / chunks);
+    int range_flag = 0;
+    // c(k) = (N w / sqrt(pi)) e^{-i k x0} e^{-w^2 (k-k0)^2}; each plane wave
+    // e^{ikx} (x <= -a) contributes e^{-ika} times its delay series
+    const double w = pk.width;
+    const double nrm = pow(2.0 * M_PI * w * w, -0.25) * w / sqrt(M_PI);
+    cd acc = mk(0.0, 0.0);
+    for (int i = i0; i < i1; ++i) {
+        const double kk = k_lo + (double)i * hk;
+        const double dk = kk - pk.k;
+        const double wt = hk * nrm * exp(-(w * dk) * (w * dk));
+        double s, co;
+        sincos(-kk * (pk.x0 + g.a), &s, &co);
+        const cd ser = delay_series(g, mk(0.0, kk), r, &range_flag);
+        acc += (wt * mk(co, s)) * ser;
+    }
+    b.Epart[(int64_t)c * (g.Nt + 1) + r] = acc;
+    if (range_flag) atomicOr(b.status, STATUS_GAMMA_RANGE);
+}
 
 __global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
                     int nk, double k_lo, double hk)
@@ -176,6 +204,9 @@ __global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_ho
     cd E;
     if (from_host == E_COPY) {
         E = b.Ebuf[r];
+    } else if (from_host == E_SUM_PARTS) {
+        E = mk(0.0, 0.0);
+        for (int c = 0; c < nk; ++c) E += b.Epart[(int64_t)c * (g.Nt + 1) + r];
     } else if (from_host == E_FROM_G) {
         // E = sqrt(Gamma/2) [G(t) - G(t - 2a)]
         E = b.Ebuf[r];
@@ -183,22 +214,6 @@ __global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_ho
         E = sqrt(0.5 * g.Gamma) * E;
     } else if (pk.incident == FDTD_INC_EXP1) {
         E = stimulated(g, r);
-    } else if (pk.incident == FDTD_INC_GAUSS2) {
-        // c(k) = (N w / sqrt(pi)) e^{-i k x0} e^{-w^2 (k-k0)^2}; each plane
-        // wave e^{ikx} (x <= -a) contributes e^{-ika} times its delay series
-        const double w = pk.width;
-        const double nrm = pow(2.0 * M_PI * w * w, -0.25) * w / sqrt(M_PI);
-        cd acc = mk(0.0, 0.0);
-        for (int i = 0; i < nk; ++i) {
-            const double kk = k_lo + (double)i * hk;
-            const double dk = kk - pk.k;
-            const double wt = hk * nrm * exp(-(w * dk) * (w * dk));
-            double s, c;
-            sincos(-kk * (pk.x0 + g.a), &s, &c);
-            const cd ser = delay_series(g, mk(0.0, kk), r, &range_flag);
-            acc += (wt * mk(c, s)) * ser;
-        }
-        E = acc;
     } else {
         // plane wave (A = 1) or exponential packet (A = i sqrt(alpha G))
         cd lam = mk(0.0, pk.k);
@@ -330,7 +345,15 @@ int launch_boundary_E(fdtd_ctx* c, int mode)
     const int64_t n = c->g.Nt + 1;
     int nk = 0;
     double k_lo = 0.0, hk = 0.0;
-    if (mode == E_COMPUTE && c->p.incident == FDTD_INC_GAUSS2) gauss_nodes(c, &nk, &k_lo, &hk);
+    if (mode == E_COMPUTE && c->p.incident == FDTD_INC_GAUSS2) {
+        gauss_nodes(c, &nk, &k_lo, &hk);
+        if (!c->b.Epart) return FDTD_EINVAL;
+        const int chunks = nk < EPART_CHUNKS ? nk : EPART_CHUNKS;
+        hipLaunchKernelGGL(k_E_part, dim3((unsigned)((n + 63) / 64), (unsigned)chunks), dim3(64), 0, c->stream, c->g,
+                           c->pk, c->b, nk, k_lo, hk, chunks);
+        mode = E_SUM_PARTS;
+        nk = chunks;
+    }
     // small E-threads blocks: the work per row grows with r, so spread rows
     hipLaunchKernelGGL(k_E, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, c->stream, c->g, c->pk, c->b,
                        mode, c->nblk, nk, k_lo, hk);

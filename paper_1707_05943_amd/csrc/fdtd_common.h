@@ -76,6 +76,7 @@ struct Packet {           // incident packet phi and the exact-solution prefacto
 // f = (Gamma/2) G(. - 2a) + phi(-a - .) is a polynomial of degree < ODE_P on
 // the step.
 constexpr int ODE_P = 16;
+constexpr int EPART_CHUNKS = 16;
 struct OdeTab {
     double tau[ODE_P + 1];
     cd ew[ODE_P + 1];
@@ -96,6 +97,8 @@ struct Bufs {
     cd* Ebuf;        // host-supplied E staging (Nt+1); G(t_r) of the delay-equation boundary
     int* status;     // device error flags
     cd* Gn;          // delay-equation boundary: G at the nodes of the last D+1 steps ((D+1) x ODE_P)
+    cd* Epart;       // series boundary of the Gaussian: partial sums over chunks of Fourier nodes
+                     // (EPART_CHUNKS x (Nt+1)); NULL for the other boundaries
     OdeTab* ode;     // its step weights
 };
 

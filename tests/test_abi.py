@@ -71,7 +71,8 @@ def test_workspace_size_counts_the_ring():
         ring = rows * (inst.Nx + 1) * 16 + rows * (inst.D + 1) * 16     # ring and its diagonal strip copy
         tables = (inst.Nt + 1) * (16 * 4 + 8 * (2 + plan["nwg"])) + (inst.Nx + 1) * 16
         ode = (inst.D + 1) * 16 * 16 + 17 * 16 * 16 + 17 * 24 + 1024    # delay-equation nodes, weights, record
-        assert ring <= n <= ring + tables + ode + 16 * 256
+        parts = 16 * (inst.Nt + 1) * 16                                   # Gaussian series: partial sums per node chunk
+        assert ring <= n <= ring + tables + ode + parts + 16 * 256
     assert fdtd.workspace_size(W.large_gauss()) < 50 * 2**30     # ~42 GB ring + 1.6 GB strip copy
 
 
