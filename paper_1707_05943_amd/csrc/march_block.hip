@@ -55,6 +55,7 @@ namespace {
 constexpr int NT = BM_THREADS;
 constexpr int K = BM_K;
 constexpr int NW = NT / 64;
+constexpr int DSTAGE = 64 * K * NW + 8;        // delay-row stage entries (64 K NW + 1, padded)
 constexpr int TBL = 1608;                  // LDS table entries (>= BM_CAP + BM_TMAX + 2, and 2 x (NT/2 K + BM_TMAX + 2))
 
 __device__ inline cd zero() { return mk(0.0, 0.0); }
@@ -212,7 +213,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 // delay-row buffers rotate instead of being copied.
 __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                          const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
-                                         int64_t rb, int H1, int nst)
+                                         int64_t rb, int H1, int nst, cd (*dstage)[DSTAGE])
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t D = g.D, C = g.C;
@@ -220,7 +221,6 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
     const bool live = j0 <= jmax;
     const unsigned own = (unsigned)(j0 * 16);                 // byte offset of column j0 in a row
-    const unsigned dly = (unsigned)((j0 - 1 - D) * 16);       // ... of column j0-1-D (>= 1: j0 > 2D)
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     cd ap[K];                                                 // alpha^(i+1)
     #pragma unroll
@@ -233,23 +233,40 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     auto ring_row = [&](int64_t sl) -> const char* {
         return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
     };
-    // (rows before t = 0 are zero, a uniform branch; lanes past the range
-    // read a valid entry, which only feeds dropped cells: no value selects,
-    // so the loads stay in flight until the values are used)
-    const unsigned dly_ok = live ? dly : 16u;
-    auto load4 = [&](cd (&dst)[K + 1], int64_t sl) {
+    // Delay rows pass through LDS: entry s of a stage holds delay column
+    // d0 + s (d0 = lo-1-D, all > 0 since lo > 2D); thread t needs entries
+    // Kt .. Kt+K.  Each wave fetches 64 consecutive entries per load (its
+    // 64K entries, and entry 64 K NW by every lane of the last wave), a row
+    // ahead, and stores them to the stage before the row's barrier.
+    const int64_t d0 = S.lo - 1 - D;
+    const int64_t dmax = jmax - D - d0;                      // last entry any thread uses
+    cd Rn[K + 1];
+    auto fetch = [&](int64_t sl) {
         if (uni((int)sl) < 0) {
             #pragma unroll
-            for (int i = 0; i <= K; ++i) dst[i] = zero();
+            for (int i = 0; i <= K; ++i) Rn[i] = zero();
         } else {
-            const char* rp = ring_row(sl) + dly_ok;
+            const cd* rp = reinterpret_cast<const cd*>(ring_row(sl)) + d0;
             #pragma unroll
-            for (int i = 0; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
+            for (int i = 0; i < K; ++i) {
+                const int64_t e = 64 * (K * wv + i) + lane;
+                Rn[i] = rp[e < dmax ? e : dmax];
+            }
+            const int64_t e = 64 * K * NW;
+            Rn[K] = rp[e < dmax ? e : dmax];
         }
     };
+    auto put = [&](cd* st) {
+        #pragma unroll
+        for (int i = 0; i < K; ++i) st[64 * (K * wv + i) + lane] = Rn[i];
+        if (wv == NW - 1 && lane == 63) st[64 * K * NW] = Rn[K];
+    };
+    auto take = [&](cd (&dst)[K + 1], const cd* st) {
+        #pragma unroll
+        for (int i = 0; i <= K; ++i) dst[i] = st[K * tid + i];
+    };
 
-    // the base row ra-1 (own columns and the one to the left) and the delay
-    // rows of row ra
+    // the base row ra-1 (own columns and the one to the left)
     cd up[K + 1];
     {
         const char* rp = ring_row((ra - 1) % g.R) + own;
@@ -259,19 +276,29 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
             up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
         }
     }
-    // delay rows two ahead: at row r the buffers hold rows r-D-1, r-D and
-    // r+1-D (in flight), and row r+2-D is requested
-    cd X[K + 1], Y[K + 1], Z[K + 1], V[K + 1];
-    load4(X, slot_or_neg(ra - 1 - D, g.R));
-    load4(Y, slot_or_neg(ra - D, g.R));
-    if (ra + 1 <= rb) load4(Z, rinfo[0].slot_pf);
+    // the delay rows of row ra (ra-1-D and ra-D) through the stages, and row
+    // ra+1-D in flight
+    cd X[K + 1], Y[K + 1];
+    fetch(slot_or_neg(ra - 1 - D, g.R));
+    put(dstage[1]);
+    fetch(slot_or_neg(ra - D, g.R));
+    put(dstage[0]);
+    __syncthreads();
+    take(X, dstage[1]);
+    __syncthreads();                                          // stage 1 is refilled by the first row
+    if (ra + 1 <= rb) fetch(rinfo[0].slot_pf);
 
-    auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
+    // row r: A holds delay row r-1-D, Bv receives row r-D from stage (tau & 1)
+    auto step = [&](int64_t r, const cd (&A)[K + 1], cd (&Bv)[K + 1]) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        if (r + 2 <= rb) load4(N, rinfo[tau + 1].slot_pf);
+        take(Bv, dstage[par]);
+        if (r + 1 <= rb) {
+            put(dstage[par ^ 1]);                     // row r+1-D, visible after this row's barrier
+            if (r + 2 <= rb) fetch(rinfo[tau + 1].slot_pf);
+        }
         // beta of the three columns
         cd p[K + 1];
         #pragma unroll
@@ -322,11 +349,9 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (lane == 63) pe_lds[tau][wv] = pe;
     };
 
-    for (int64_t r = ra; r <= rb; r += 4) {
-        step(r, X, Y, V);
-        if (r + 1 <= rb) step(r + 1, Y, Z, X);
-        if (r + 2 <= rb) step(r + 2, Z, V, Y);
-        if (r + 3 <= rb) step(r + 3, V, X, Z);
+    for (int64_t r = ra; r <= rb; r += 2) {
+        step(r, X, Y);
+        if (r + 1 <= rb) step(r + 1, Y, X);
     }
 }
 
@@ -664,6 +689,7 @@ __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64
 }
 
 struct Shared {
+    cd dstage[2][DSTAGE];        // far workgroups: the next delay rows, fetched with coalesced loads
     cd wave_tot[2][NW];
     double pe_lds[BM_TMAX][NW];
     cd win[BM_TMAX][BM_TMAX];
@@ -798,7 +824,7 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.lo = P.win_lo;
     W.row0 = ra;
 
-    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
+    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.dstage);
     else if (is_strip) strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst);
     else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
     __syncthreads();
