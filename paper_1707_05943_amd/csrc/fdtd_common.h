@@ -172,6 +172,7 @@ constexpr int BM_THREADS = 512;
 constexpr int BM_K = 3;
 constexpr int BM_CAP = BM_THREADS * BM_K;      // columns a workgroup can hold in one row
 constexpr int BM_TMAX = 32;                    // largest block of rows (LDS window is BM_TMAX x BM_TMAX)
+constexpr int BM_NEAR_CAP = 1024;              // columns a near workgroup may span (three tables, four row stages in LDS)
 
 // Planner knobs: workgroups the instance should spread over (about one per
 // compute unit when it runs alone), the largest block of rows, and the widest

@@ -55,8 +55,11 @@ namespace {
 constexpr int NT = BM_THREADS;
 constexpr int K = BM_K;
 constexpr int NW = NT / 64;
-constexpr int DSTAGE = 64 * K * NW + 8;        // delay-row stage entries (64 K NW + 1, padded)
+constexpr int DSTAGE = 64 * K * NW + 8;        // row stage entries for a whole workgroup (64 K NW + K, padded)
+constexpr int NSTAGE = BM_NEAR_CAP + 136;      // near stage: K + BM_NEAR_CAP + 1 entries, a pad of 64, 64 carry copies
+constexpr int NCARRY = NSTAGE - 64;
 constexpr int TBL = 1608;                  // LDS table entries (>= BM_CAP + BM_TMAX + 2, and 2 x (NT/2 K + BM_TMAX + 2))
+constexpr int TBLN = BM_NEAR_CAP + BM_TMAX + 8;  // near workgroups' table entries
 
 __device__ inline cd zero() { return mk(0.0, 0.0); }
 __device__ inline int64_t dec_slot(int64_t s, int64_t R) { return s == 0 ? R - 1 : s - 1; }
@@ -177,6 +180,7 @@ struct RowInfo {
     cd ga, gb;                   // g8r Et[r-1-D], g8r Et[r-D]
     cd hp;                       // cinv (-Gamma/2) half_pr
     cd psi0;                     // psi(0, r) = Phi[r] Et[r]
+    cd z0, z1;                   // psi(0, r-D), psi(0, r-1-D) (zero before t = 0)
 };
 
 // A thread's column range and role.  Threads t0 .. t0+nt-1 of the workgroup
@@ -205,12 +209,69 @@ __device__ __forceinline__ void cmac(cd& acc, const cd a, const cd b)
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Rows staged through LDS.  Row values a workgroup needs at K columns'
+// stride per lane are fetched with coalesced loads instead: the nw waves of
+// a segment load entries 0 .. 64 K nw - 1 of the row (the planner keeps a
+// segment's entries below that), wave v entries 64 (K v + i) + lane, and
+// write them to a stage; each thread reads its K+1 entries back after a
+// barrier.  Entry e reads src[clamp(e, elo, ehi)], so every load is from a
+// valid address and no value is selected before it is used; entries outside
+// [elo, ehi] are never used.  Stage rho holds what row rho reads.  Row r
+// takes stage r before its barrier, writes stage r+2 (fetched by row r-1)
+// into the same buffer after it, then its outputs, and last issues the loads
+// of stage r+3.  Every fetched value is written to the stage on every path,
+// unpredicated, so that when a row's stores and the next loads issue no load
+// is still outstanding: the loads a row waits for are the only ones in
+// flight, and they have a whole row to arrive.
+__device__ __forceinline__ void stage_fetch(cd (&Rn)[K], const cd* src, int64_t elo, int64_t ehi, int v, int lane)
+{
+    #pragma unroll
+    for (int i = 0; i < K; ++i) {
+        int64_t e = 64 * (K * v + i) + lane;
+        e = e < elo ? elo : (e > ehi ? ehi : e);
+        const double2 x = *reinterpret_cast<const double2*>(src + e);
+        Rn[i] = mk(x.x, x.y);
+    }
+}
+template <int N>
+__device__ __forceinline__ void stage_zero(cd (&Rn)[N])
+{
+    #pragma unroll
+    for (int i = 0; i < N; ++i) Rn[i] = zero();
+}
+// a stage that holds every entry of the segment's waves
+__device__ __forceinline__ void stage_put(cd* st, const cd (&Rn)[K], int v, int lane)
+{
+    #pragma unroll
+    for (int i = 0; i < K; ++i)
+        *reinterpret_cast<double2*>(st + 64 * (K * v + i) + lane) = make_double2(Rn[i].re, Rn[i].im);
+}
+// a stage that holds entries 0..n and a pad of 64 after them: entries beyond
+// n land in the pad, one slot per lane
+__device__ __forceinline__ void stage_put_pad(cd* st, const cd (&Rn)[K], int64_t n, int v, int lane)
+{
+    #pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t e = 64 * (K * v + i) + lane;
+        *reinterpret_cast<double2*>(st + (e <= n ? e : n + 1 + lane)) = make_double2(Rn[i].re, Rn[i].im);
+    }
+}
+__device__ __forceinline__ void stage_take(cd (&dst)[K + 1], const cd* st)
+{
+    #pragma unroll
+    for (int i = 0; i <= K; ++i) dst[i] = st[i];
+}
+__device__ __forceinline__ cd ld2(const cd* p)
+{
+    const double2 x = *reinterpret_cast<const double2*>(p);
+    return mk(x.x, x.y);
+}
+
 // The rows of a workgroup whose every column lies beyond 2D: all source
 // terms are exact (tables Et[q] - Et[q+D] and Phi[q] in LDS), the delay rows
 // are the only reads of the ring.  The workgroup's range starts a halo left
 // of its own columns (the trapezoid moves H+1 columns right per row), so the
-// carry into its first column is zero.  Rows go in threes so that the three
-// delay-row buffers rotate instead of being copied.
+// carry into its first column is zero.
 __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                          const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
                                          int64_t rb, int H1, int nst, cd (*dstage)[DSTAGE])
@@ -233,72 +294,47 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     auto ring_row = [&](int64_t sl) -> const char* {
         return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
     };
-    // Delay rows pass through LDS: entry s of a stage holds delay column
-    // d0 + s (d0 = lo-1-D, all > 0 since lo > 2D); thread t needs entries
-    // Kt .. Kt+K.  Each wave fetches 64 consecutive entries per load (its
-    // 64K entries, and entry 64 K NW by every lane of the last wave), a row
-    // ahead, and stores them to the stage before the row's barrier.
+    // stage rho: delay row rho - D, entry s is column d0 + s (d0 = lo-1-D > D);
+    // thread t reads entries Kt .. Kt+K
     const int64_t d0 = S.lo - 1 - D;
-    const int64_t dmax = jmax - D - d0;                      // last entry any thread uses
-    cd Rn[K + 1];
-    auto fetch = [&](int64_t sl) {
-        if (uni((int)sl) < 0) {
-            #pragma unroll
-            for (int i = 0; i <= K; ++i) Rn[i] = zero();
-        } else {
-            const cd* rp = reinterpret_cast<const cd*>(ring_row(sl)) + d0;
-            #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int64_t e = 64 * (K * wv + i) + lane;
-                Rn[i] = rp[e < dmax ? e : dmax];
-            }
-            const int64_t e = 64 * K * NW;
-            Rn[K] = rp[e < dmax ? e : dmax];
-        }
-    };
-    auto put = [&](cd* st) {
-        #pragma unroll
-        for (int i = 0; i < K; ++i) st[64 * (K * wv + i) + lane] = Rn[i];
-        if (wv == NW - 1 && lane == 63) st[64 * K * NW] = Rn[K];
-    };
-    auto take = [&](cd (&dst)[K + 1], const cd* st) {
-        #pragma unroll
-        for (int i = 0; i <= K; ++i) dst[i] = st[K * tid + i];
+    const int64_t nd = jmax - D - d0;                         // last entry any thread uses
+    const int ed = live ? K * tid : 0;
+    auto fetch = [&](cd (&R)[K], int64_t sl) __attribute__((always_inline)) {
+        if (uni((int)sl) < 0) stage_zero(R);
+        else stage_fetch(R, reinterpret_cast<const cd*>(ring_row(sl)) + d0, 0, nd, wv, lane);
     };
 
-    // the base row ra-1 (own columns and the one to the left)
-    cd up[K + 1];
+    // the base row ra-1 (own columns and the one to the left) and delay row
+    // ra-1-D, read directly; stages ra and ra+1 filled, stage ra+2 in flight
+    cd up[K + 1], X[K + 1], Y[K + 1], Rn[K];
     {
         const char* rp = ring_row((ra - 1) % g.R) + own;
+        const int64_t sx = slot_or_neg(ra - 1 - D, g.R);
+        const cd* xp = reinterpret_cast<const cd*>(ring_row(sx < 0 ? 0 : sx)) + d0;
         #pragma unroll
         for (int i = 0; i <= K; ++i) {
             const int64_t j = j0 - 1 + i;
             up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
+            const int64_t e = ed + i;
+            X[i] = ld2(xp + (e < nd ? e : nd));
         }
+        if (uni((int)sx) < 0) stage_zero(X);
+        cd R0[K], R1[K];
+        fetch(R0, slot_or_neg(ra - D, g.R));
+        if (ra + 1 <= rb) fetch(R1, rinfo[0].slot_pf);
+        stage_put(dstage[0], R0, wv, lane);
+        if (ra + 1 <= rb) stage_put(dstage[1], R1, wv, lane);
+        if (ra + 2 <= rb) fetch(Rn, rinfo[1].slot_pf);
     }
-    // the delay rows of row ra (ra-1-D and ra-D) through the stages, and row
-    // ra+1-D in flight
-    cd X[K + 1], Y[K + 1];
-    fetch(slot_or_neg(ra - 1 - D, g.R));
-    put(dstage[1]);
-    fetch(slot_or_neg(ra - D, g.R));
-    put(dstage[0]);
     __syncthreads();
-    take(X, dstage[1]);
-    __syncthreads();                                          // stage 1 is refilled by the first row
-    if (ra + 1 <= rb) fetch(rinfo[0].slot_pf);
 
-    // row r: A holds delay row r-1-D, Bv receives row r-D from stage (tau & 1)
-    auto step = [&](int64_t r, const cd (&A)[K + 1], cd (&Bv)[K + 1]) {
+    // row r: A holds delay row r-1-D, Bv receives row r-D from stage r
+    auto step = [&](int64_t r, const cd (&A)[K + 1], cd (&Bv)[K + 1]) __attribute__((always_inline)) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        take(Bv, dstage[par]);
-        if (r + 1 <= rb) {
-            put(dstage[par ^ 1]);                     // row r+1-D, visible after this row's barrier
-            if (r + 2 <= rb) fetch(rinfo[tau + 1].slot_pf);
-        }
+        stage_take(Bv, dstage[par] + ed);
         // beta of the three columns
         cd p[K + 1];
         #pragma unroll
@@ -325,6 +361,7 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
         __syncthreads();
+        stage_put(dstage[par], Rn, wv, lane);           // stage r+2 (not read if r+2 > rb)
         cd cin = prevx;
         if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
         // the row's values, the ring, P_e
@@ -347,6 +384,7 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         }
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
+        if (r + 3 <= rb) fetch(Rn, rinfo[tau + 2].slot_pf);
     };
 
     for (int64_t r = ra; r <= rb; r += 2) {
@@ -355,22 +393,22 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     }
 }
 
-// The rows of a near workgroup (columns D+1 .. 2D + hmax).  The delay
-// corners are ring values (column 0, which only the region's first column
-// reads, is the exact solution); the first source term is exact, the second
-// reads the mirror pair psi(2D-j, q+D), psi(2D-j+1, q+D) from the diagonal
-// copy for j < 2D, with psi(0, q+D) exact at j = 2D and both exact beyond.
+// The rows of a near workgroup (columns D+1 .. 2D + hmax, spanning at most
+// BM_NEAR_CAP columns).  The delay corners are ring values (column 0, which
+// only the region's first column reads, is the exact solution); the first
+// source term is exact, the second reads the mirror pair psi(2D-j, q+D),
+// psi(2D-j+1, q+D) from the diagonal copy for j < 2D, with psi(0, q+D)
+// exact at j = 2D and both exact beyond.  The delay rows, the diagonal-copy
+// rows and (first workgroup) the carry psi(D, r) pass through LDS stages.
 __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                           const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
-                                          int64_t rb, int H1, int nst)
+                                          int64_t rb, int H1, int nst, cd (*dstage)[NSTAGE], cd (*mstage)[NSTAGE])
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t D = g.D, C = g.C, Mc = g.Mc;
     const int64_t j0 = S.lo + (int64_t)K * tid;
     const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
     const bool live = j0 <= jmax;
-    const int64_t dcol = j0 - 1 - D;                          // first delay column (0 only for j0 = D+1)
-    const unsigned dly = (unsigned)(dcol * 16);
     const unsigned own = (unsigned)(j0 * 16);
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
@@ -382,82 +420,103 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     const cd* tP = S.tP;
     const cd* tE2 = S.tE2;
     const bool first = (tid == 0);
+    const bool col0 = first && S.lo == D + 1;                 // reads the delay corners at column 0
+    const bool carry = first && S.exact;                      // takes psi(lo-1, r) from the strip
 
     auto ring_row = [&](int64_t sl) -> const char* {
         return reinterpret_cast<const char*>(b.ring + (int64_t)uni((int)sl) * C);
     };
-    // delay row rho (ring slot sl; sl < 0 before t = 0)
-    const unsigned dly_ok = live ? dly : 16u;
-    auto load4 = [&](cd (&dst)[K + 1], int64_t sl, int64_t rho) {
-        if (uni((int)sl) < 0) {
-            #pragma unroll
-            for (int i = 0; i <= K; ++i) dst[i] = zero();
-        } else {
-            const char* rp = ring_row(sl) + dly_ok;
-            #pragma unroll
-            for (int i = 1; i <= K; ++i) dst[i] = *reinterpret_cast<const cd*>(rp + 16 * i);
-            // column 0 (the region's first column only) is the exact solution
-            if (dcol == 0) dst[0] = b.Phi[rho] * b.Et[rho];
-            else dst[0] = *reinterpret_cast<const cd*>(rp);
-        }
+    // stage rho, delay part: delay row rho - D, entry s is column d0 + s
+    // (d0 = lo-1-D >= 0); thread t reads entries Kt .. Kt+K.  Entries
+    // NCARRY.. hold psi(lo-1, rho), one copy per lane (the first workgroup's
+    // carry; the others load and store it too, so that no access is predicated).
+    const int64_t d0 = S.lo - 1 - D;
+    const int64_t nd = jmax - D - d0;
+    const int ed = live ? K * tid : 0;
+    // stage rho, mirror part: the Md row of diagonal rho - D, entry s is its
+    // column cm + s (cm = 2D - jmax), stored K entries in; cell j0 + i reads
+    // entry jmax - j0 - i (mirror psi(2D-j, .)) of stage r and entry
+    // jmax - j0 - i + 1 (psi(2D-j+1, .)) of stage r-1.  Columns outside 1..D
+    // are never used.
+    const int64_t cm = 2 * D - jmax;
+    const int64_t nm = jmax - S.lo + 1;
+    const int64_t mlo = cm < 1 ? 1 - cm : 0;
+    const int64_t mhi = D - cm < nm ? D - cm : nm;
+    const int em = K + (live ? (int)(jmax - j0) - (K - 1) : 0);
+    const unsigned cofs = (unsigned)((S.lo - 1) * 16);
+    cd Rd[K], Rm[K], Rc;
+    // the loads of stage rho (ring slot of delay row rho - D, row rho's slot)
+    auto fetch = [&](cd (&Pd)[K], cd (&Pm)[K], cd& Pc, int64_t sd, int64_t sr) __attribute__((always_inline)) {
+        if (uni((int)sd) < 0) stage_zero(Pd);
+        else stage_fetch(Pd, reinterpret_cast<const cd*>(ring_row(sd)) + d0, 0, nd, wv, lane);
+        stage_fetch(Pm, b.Md + (int64_t)uni((int)sr) * Mc + cm, mlo, mhi, wv, lane);
+        Pc = ld2(reinterpret_cast<const cd*>(ring_row(sr) + cofs));
     };
-    // mirror pair of row rr for the cells with j <= 2D: psi(2D-j, q+D) and
-    // psi(2D-j+1, q+D), q = rr - j; at j = 2D the first is exact and Phi[q+D]
-    // is loaded (its Et[q+D] factor is applied where it is used).  One load per
-    // value from a chosen address, so the values are not waited for here;
-    // cells without a mirror read a valid entry and are dropped where used.
-    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB, int64_t rr) {
-        const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
-        const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
-        #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int64_t c = 2 * D - (j0 + i);
-            const bool ok = live && j0 + i <= jmax && c >= 0;
-            const int64_t qd = rr - (j0 + i) + D;
-            const cd* pa = !ok ? rA + 1 : (c >= 1 ? rA + c : b.Phi + (qd >= 0 ? qd : 0));
-            const cd* pb = ok ? rB + c + 1 : rB + 1;
-            mA[i] = *pa;
-            mB[i] = *pb;
-        }
+    auto put = [&](int par, const cd (&Pd)[K], const cd (&Pm)[K], const cd& Pc) __attribute__((always_inline)) {
+        stage_put_pad(dstage[par], Pd, nd, wv, lane);
+        stage_put_pad(mstage[par] + K, Pm, nm, wv, lane);
+        dstage[par][NCARRY + lane] = Pc;
     };
 
-    cd up[K + 1];
+    // base row ra-1, delay row ra-1-D and the second mirror values of row ra
+    // (Md row of diagonal ra-1-D) read directly; stages ra, ra+1 filled,
+    // stage ra+2 in flight
+    cd up[K + 1], X[K + 1], Y[K + 1];
+    cd MB0[K], MB1[K];
     {
         const char* rp = ring_row((ra - 1) % g.R) + own;
+        const int64_t sx = slot_or_neg(ra - 1 - D, g.R);
+        const cd* xp = reinterpret_cast<const cd*>(ring_row(sx < 0 ? 0 : sx)) + d0;
+        const cd* mp = b.Md + (int64_t)uni((int)rinfo[0].slot_m1) * Mc + cm;
         #pragma unroll
         for (int i = 0; i <= K; ++i) {
             const int64_t j = j0 - 1 + i;
             up[i] = (live && j <= jmax) ? *reinterpret_cast<const cd*>(rp + 16 * (i - 1)) : zero();
+            const int64_t e = ed + i;
+            X[i] = ld2(xp + (e < nd ? e : nd));
         }
+        if (uni((int)sx) < 0) stage_zero(X);
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            int64_t e = em - K + (K - i);                     // entry jmax - j0 - i + 1
+            e = e < mlo ? mlo : (e > mhi ? mhi : e);
+            MB0[i] = ld2(mp + e);
+        }
+        cd P0[K], P1[K], M0[K], M1[K], c0, c1;
+        fetch(P0, M0, c0, slot_or_neg(ra - D, g.R), rinfo[0].slot);
+        if (ra + 1 <= rb) fetch(P1, M1, c1, rinfo[0].slot_pf, rinfo[1].slot);
+        put(0, P0, M0, c0);
+        if (ra + 1 <= rb) put(1, P1, M1, c1);
+        if (ra + 2 <= rb) fetch(Rd, Rm, Rc, rinfo[1].slot_pf, rinfo[2].slot);
     }
-    cd X[K + 1], Y[K + 1], Z[K + 1];
-    load4(X, slot_or_neg(ra - 1 - D, g.R), ra - 1 - D);
-    load4(Y, slot_or_neg(ra - D, g.R), ra - D);
-    cd mA[K], mB[K], nA[K], nB[K];
-    load_m(mA, mB, rinfo[0].slot, rinfo[0].slot_m1, ra);
-    // the exact segment's carry psi(lo-1, r) (written by the strip a launch
-    // earlier), a row ahead
-    const unsigned cofs = (unsigned)((S.lo - 1) * 16);
-    cd cnext = zero();
-    if (first && S.exact) cnext = *reinterpret_cast<const cd*>(ring_row(rinfo[0].slot) + cofs);
+    __syncthreads();
 
-    auto step = [&](int64_t r, const cd (&A)[K + 1], const cd (&Bv)[K + 1], cd (&N)[K + 1]) {
+    // row r: A holds delay row r-1-D, Bv receives row r-D; mB holds the
+    // second mirror values of row r, mBn receives those of row r+1
+    auto step = [&](int64_t r, const cd (&A)[K + 1], cd (&Bv)[K + 1], const cd (&mB)[K], cd (&mBn)[K])
+                    __attribute__((always_inline)) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         const int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        const cd carry0 = cnext;
-        if (r + 1 <= rb) {
-            load4(N, ri.slot_pf, r + 1 - D);
-            const RowInfo& rn = rinfo[tau + 1];
-            load_m(nA, nB, rn.slot, rn.slot_m1, r + 1);
-            if (first && S.exact) cnext = *reinterpret_cast<const cd*>(ring_row(rn.slot) + cofs);
+        stage_take(Bv, dstage[par] + ed);
+        const cd carry0 = dstage[par][NCARRY];
+        cd mA[K];
+        {
+            cd V[K + 1];
+            stage_take(V, mstage[par] + em);
+            #pragma unroll
+            for (int i = 0; i < K; ++i) {
+                mA[i] = V[K - 1 - i];
+                mBn[i] = V[K - i];
+            }
         }
         cd p[K + 1];
         #pragma unroll
         for (int i = 0; i <= K; ++i) p[i] = A[i] + Bv[i];
+        if (col0) p[0] = ri.z1 + ri.z0;                      // column 0 of rows r-1-D, r-D, exact
         const int64_t t0 = r - j0 - S.qa;
-        const cd g8r = ri.g8r, krc = ri.krc, drc = ri.drc, hp = ri.hp;
+        const cd g8r = ri.g8r, krc = ri.krc, drc = ri.drc, hp = ri.hp, z0 = ri.z0;
         cd u[K];
         #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -473,8 +532,9 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             cmac(v, krc, et);                           // first source, exact
             cmac(v, drc, ph);
             if (j <= 2 * D) {
-                // second source: -(G/2)[ (m0 + m1)/2 - Et[q+D] half_pr ]
-                const cd m0 = (j == 2 * D) ? mA[i] * et2 : mA[i];
+                // second source: -(G/2)[ (m0 + m1)/2 - Et[q+D] half_pr ], with
+                // m0 = psi(0, r-D) exact at j = 2D
+                const cd m0 = (j == 2 * D) ? z0 : mA[i];
                 cmac(v, -c4, (q + D >= 0) ? m0 + mB[i] : zero());
                 cmac(v, -hp, et2);
             } else {
@@ -485,11 +545,12 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         #pragma unroll
         for (int i = 1; i < K; ++i) cmac(u[i], al, u[i - 1]);
         cd x = u[K - 1];
-        if (first && S.exact) cmac(x, ap[K - 1], carry0);
+        if (carry) cmac(x, ap[K - 1], carry0);
         x = wave_scan(x, pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
         __syncthreads();
+        put(par, Rd, Rm, Rc);                                 // stage r+2 (not read if r+2 > rb)
         cd cin = prevx;
         if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
         if (first) cin = S.exact ? carry0 : zero();
@@ -512,17 +573,12 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         }
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
-        #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            mA[i] = nA[i];
-            mB[i] = nB[i];
-        }
+        if (r + 3 <= rb) fetch(Rd, Rm, Rc, rinfo[tau + 2].slot_pf, rinfo[tau + 3].slot);
     };
 
-    for (int64_t r = ra; r <= rb; r += 3) {
-        step(r, X, Y, Z);
-        if (r + 1 <= rb) step(r + 1, Y, Z, X);
-        if (r + 2 <= rb) step(r + 2, Z, X, Y);
+    for (int64_t r = ra; r <= rb; r += 2) {
+        step(r, X, Y, MB0, MB1);
+        if (r + 1 <= rb) step(r + 1, Y, X, MB1, MB0);
     }
 }
 
@@ -530,13 +586,13 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
 // workgroups and the cone.  A strip cell's four delay corners lie at
 // x <= -a, so with q = r - j they are Et[r-1-D] (Phi[q] + Phi[q-1]) and
 // Et[r-D] (Phi[q+1] + Phi[q]) from the LDS table; the mirror reads
-// psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (prefetched a row
-// ahead) or, for the strip's first columns, from the LDS window of the
+// psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (its rows staged
+// through LDS) or, for the strip's first columns, from the LDS window of the
 // current block.  The table here starts one entry before q = S.qa + 1.
 __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw,
                                            cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
                                            const Seg& S, int64_t ra, int64_t rb, int H1, int T, int cone,
-                                           int use_win, int nst)
+                                           int use_win, int nst, cd (*mstage)[DSTAGE])
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t D = g.D, C = g.C, Mc = g.Mc;
@@ -553,23 +609,26 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const cd* tP = S.tP;
     const bool first = (tid == S.t0);
 
-    // mirror values of row r for this thread's cells: diagonals r-D (Md row
-    // slot(r)) at column D-j, and r-D-1 (slot(r-1)) at column D-j+1
-    // (one load per value from a valid address, no selects: cells without a
-    // mirror read are dropped, or replaced, where the values are used)
-    auto load_m = [&](cd (&mA)[K], cd (&mB)[K], int64_t sA, int64_t sB) {
-        const cd* rA = b.Md + (int64_t)uni((int)sA) * Mc;
-        const cd* rB = b.Md + (int64_t)uni((int)sB) * Mc;
-        #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int64_t c = D - (j0 + i);
-            const bool ok = live && j0 + i <= jmax;
-            mA[i] = rA[(ok && c >= 1) ? c : 1];
-            mB[i] = rB[ok ? c + 1 : 1];
-        }
+    // stage rho: the Md row of diagonal rho - D, entry s is its column
+    // cm + s (cm = D - jmax), stored K entries in, each segment in its own
+    // half of the stage when the workgroup has two; cell j0 + i reads entry
+    // jmax - j0 - i (psi(D-j, .)) of stage r and entry jmax - j0 - i + 1
+    // (psi(D-j+1, .)) of stage r-1.  Column 0 (j = D) is exact and never read.
+    const int sv = wv - S.w0;                                 // the segment's waves
+    const int soff = (S.t0 ? DSTAGE / 2 : 0) + K;
+    const int64_t cm = D - jmax;
+    const int64_t nm = jmax - S.lo + 1;
+    const int64_t mlo = cm < 1 ? 1 - cm : 0;
+    const int em = soff + (live ? (int)(jmax - j0) - (K - 1) : 0);
+    cd Rm[K];
+    auto fetch = [&](cd (&R)[K], int64_t sl) __attribute__((always_inline)) {
+        stage_fetch(R, b.Md + (int64_t)uni((int)sl) * Mc + cm, mlo, nm, sv, lane);
     };
 
+    // base row ra-1 and the second mirror values of row ra (Md row of
+    // diagonal ra-1-D) read directly; stages ra, ra+1 filled, ra+2 in flight
     cd up[K + 1];
+    cd MB0[K], MB1[K];
     {
         const cd* rp = b.ring + (int64_t)uni((int)((ra - 1) % g.R)) * C;
         #pragma unroll
@@ -577,21 +636,39 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             const int64_t j = j0 - 1 + i;
             up[i] = (live && j <= jmax) ? (j >= 1 ? rp[j] : phi_at(b, ra - 1) * et_at(b, ra - 1)) : zero();
         }
+        const cd* mp = b.Md + (int64_t)uni((int)rinfo[0].slot_m1) * Mc + cm;
+        #pragma unroll
+        for (int i = 0; i < K; ++i) {
+            int64_t e = em - soff + (K - i);                  // entry jmax - j0 - i + 1
+            e = e < mlo ? mlo : (e > nm ? nm : e);
+            MB0[i] = ld2(mp + e);
+        }
+        cd P0[K], P1[K];
+        fetch(P0, rinfo[0].slot);
+        if (ra + 1 <= rb) fetch(P1, rinfo[1].slot);
+        stage_put(mstage[0] + soff, P0, sv, lane);
+        if (ra + 1 <= rb) stage_put(mstage[1] + soff, P1, sv, lane);
+        if (ra + 2 <= rb) fetch(Rm, rinfo[2].slot);
     }
-    cd MA0[K], MB0[K], MA1[K], MB1[K];
-    load_m(MA0, MB0, rinfo[0].slot, rinfo[0].slot_m1);
+    __syncthreads();
     const int64_t R = g.R;
     int64_t sdr = ((ra - j0 + D) % R + R) % R;                  // Md row of diagonal r - j0, row by row
 
-    auto step = [&](int64_t r, const cd (&mA)[K], const cd (&mB)[K], cd (&nA)[K], cd (&nB)[K]) {
+    auto step = [&](int64_t r, const cd (&mB)[K], cd (&mBn)[K]) __attribute__((always_inline)) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
         if (cone && tid >= NT / 2 && tau > T - 2) act_lo = S.hi;        // the cone stops a row early
-        if (r + 1 <= rb) {
-            const RowInfo& rn = rinfo[tau + 1];
-            load_m(nA, nB, rn.slot, rn.slot_m1);
+        cd mA[K];
+        {
+            cd V[K + 1];
+            stage_take(V, mstage[par] + em);
+            #pragma unroll
+            for (int i = 0; i < K; ++i) {
+                mA[i] = V[K - 1 - i];
+                mBn[i] = V[K - i];
+            }
         }
         const cd ga = ri.ga, gb = ri.gb, hp = ri.hp, drc = ri.drc;
         const int64_t q0 = r - j0;
@@ -634,6 +711,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
         __syncthreads();
+        stage_put(mstage[par] + soff, Rm, sv, lane);          // stage r+2 (not read if r+2 > rb)
         cd cin = prevx;
         if (wv > S.w0) cmac(cin, lp, wave_tot[par][wv - 1]);
         if (first) cin = S.exact ? ri.psi0 : zero();
@@ -661,12 +739,13 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         }
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
+        if (r + 3 <= rb) fetch(Rm, rinfo[tau + 3].slot);
         if (use_win) __syncthreads();                 // window rows written above are read by the next row
     };
 
     for (int64_t r = ra; r <= rb; r += 2) {
-        step(r, MA0, MB0, MA1, MB1);
-        if (r + 1 <= rb) step(r + 1, MA1, MB1, MA0, MB0);
+        step(r, MB0, MB1);
+        if (r + 1 <= rb) step(r + 1, MB1, MB0);
     }
 }
 
@@ -688,12 +767,29 @@ __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64
     }
 }
 
+// LDS of a workgroup: the part its region's row loop uses, and the rest
+struct FarLds {
+    cd tab[2][TBL];              // Et[q] - Et[q+D], Phi[q]
+    cd dstage[2][DSTAGE];        // delay rows
+};
+struct NearLds {
+    cd tab[3][TBLN];             // Et[q], Phi[q], Et[q+D]
+    cd dstage[2][NSTAGE];        // delay rows
+    cd mstage[2][NSTAGE];        // diagonal-copy rows
+};
+struct StripLds {
+    cd tab[2][TBL];              // Et[q], Phi[q] (the cone's in the second halves)
+    cd win[BM_TMAX][BM_TMAX];    // the strip's right end over the block
+    cd mstage[2][DSTAGE];        // diagonal-copy rows
+};
 struct Shared {
-    cd dstage[2][DSTAGE];        // far workgroups: the next delay rows, fetched with coalesced loads
+    union {
+        FarLds f;
+        NearLds n;
+        StripLds s;
+    } u;
     cd wave_tot[2][NW];
     double pe_lds[BM_TMAX][NW];
-    cd win[BM_TMAX][BM_TMAX];
-    cd tab[3][TBL];
     RowInfo rinfo[BM_TMAX];
     Pow pw;
 };
@@ -705,8 +801,6 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
 {
     cd(*wave_tot)[NW] = sh.wave_tot;
     double(*pe_lds)[NW] = sh.pe_lds;
-    cd(*win)[BM_TMAX] = sh.win;
-    cd(*tab)[TBL] = sh.tab;
     RowInfo* rinfo = sh.rinfo;
     Pow& pw = sh.pw;
 
@@ -741,6 +835,9 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     const int nrows = (int)(rb - ra + 1);
     const int cone = is_strip && w == 0 && P.cone_mode == 1;
     const int use_win = is_strip && w == 0;
+    cd* tab0 = far ? sh.u.f.tab[0] : (is_strip ? sh.u.s.tab[0] : sh.u.n.tab[0]);
+    cd* tab1 = far ? sh.u.f.tab[1] : (is_strip ? sh.u.s.tab[1] : sh.u.n.tab[1]);
+    cd* tab2 = sh.u.n.tab[2];
 
     // this thread's segment: the whole workgroup, or (strip workgroup 0 in
     // cone mode) the first half for its columns and the second half for the cone
@@ -757,9 +854,9 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     S.write_win = use_win && (P.cone_mode == 0);
     S.use_win = use_win;
     S.qa = ra - (c1 - 1);
-    S.tE = tab[0];
-    S.tP = tab[1];
-    S.tE2 = tab[2];
+    S.tE = tab0;
+    S.tP = tab1;
+    S.tE2 = tab2;
     if (cone && threadIdx.x >= NT / 2) {
         S.t0 = NT / 2;
         S.w0 = NW / 2;
@@ -773,8 +870,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         S.write_win = 1;
         S.use_win = 0;                           // the cone's mirror reads are older than the block
         S.qa = ra - D;
-        S.tE = tab[0] + TBL / 2;
-        S.tP = tab[1] + TBL / 2;
+        S.tE = tab0 + TBL / 2;
+        S.tP = tab1 + TBL / 2;
     }
 
     // per-row values of this block, scan constants, tables
@@ -795,6 +892,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         ri.gb = ri.g8r * et_at(b, r - D);
         ri.hp = g.cinv * ((-0.5 * g.Gamma) * ri.half_pr);
         ri.psi0 = phi_at(b, r) * et_at(b, r);
+        ri.z0 = phi_at(b, r - D) * et_at(b, r - D);
+        ri.z1 = phi_at(b, r - 1 - D) * et_at(b, r - 1 - D);
         rinfo[threadIdx.x] = ri;
     }
     fill_pow(g.alpha, pw);
@@ -802,31 +901,26 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         // strip tables reach one entry beyond each end (Phi[q-1], Phi[q+1])
         S.qa -= 1;
         if (cone) {
-            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab[0], tab[1], nullptr, 0, NT / 2);
-        } else {
-            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab[0], tab[1], nullptr, 0, NT);
-        }
-        if (cone)
-            fill_tables(b, D, 0, ra - D - 1, P.cone_L0 + (rb - ra) + 2, tab[0] + TBL / 2, tab[1] + TBL / 2, nullptr,
+            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab0, tab1, nullptr, 0, NT / 2);
+            fill_tables(b, D, 0, ra - D - 1, P.cone_L0 + (rb - ra) + 2, tab0 + TBL / 2, tab1 + TBL / 2, nullptr,
                         NT / 2, NT / 2);
-    } else if (cone) {
-        fill_tables(b, D, 0, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab[0], tab[1], nullptr, 0, NT / 2);
-        fill_tables(b, D, 0, ra - D, P.cone_L0 + (rb - ra), tab[0] + TBL / 2, tab[1] + TBL / 2, nullptr, NT / 2,
-                    NT / 2);
+        } else {
+            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab0, tab1, nullptr, 0, NT);
+        }
     } else {
-        fill_tables(b, D, far, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab[0], tab[1], (far || is_strip) ? nullptr : tab[2],
-                    0, NT);
+        fill_tables(b, D, far, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab0, tab1, far ? nullptr : tab2, 0, NT);
     }
     __syncthreads();
 
     Win W;
-    W.w = win;
+    W.w = sh.u.s.win;
     W.lo = P.win_lo;
     W.row0 = ra;
 
-    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.dstage);
-    else if (is_strip) strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst);
-    else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst);
+    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage);
+    else if (is_strip)
+        strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst, sh.u.s.mstage);
+    else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
@@ -893,6 +987,11 @@ int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipS
 // column), about kn.ncu workgroups (one per compute unit for an instance that
 // runs alone; an instance of a batch asks for the widest workgroups).
 static const double MIRROR_COST = 3.5;
+// the widest column range of a workgroup (one segment) and of each half of
+// the strip's first workgroup: the row stages hold one entry less than the
+// threads' columns
+static const int64_t SPAN_CAP = BM_CAP - 1;
+static const int64_t HALF_CAP = (int64_t)(BM_THREADS / 2) * BM_K - 1;
 
 int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char* why, size_t n)
 {
@@ -906,7 +1005,7 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
         P.T = T;
         P.H = H;
         P.hmax = (H + 1) * T - 1;
-        int64_t room = BM_CAP - P.hmax;                 // owned columns a halo workgroup can hold
+        int64_t room = SPAN_CAP - P.hmax;               // owned columns a halo workgroup can hold
         if (room < 64) continue;
         // a narrower cap, but never below twice the halo
         const int64_t cap = kn.wmax > 2 * (int64_t)P.hmax ? kn.wmax : 2 * (int64_t)P.hmax;
@@ -920,6 +1019,7 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
         int64_t minw = 2 * (int64_t)P.hmax;
         if (minw < 64) minw = 64;
         if (minw > room) minw = room;
+        if (BM_NEAR_CAP - (int64_t)P.hmax < minw) continue;
         double budget = (MIRROR_COST * (double)(D + near_cols) + (double)far_cols) / NCU;
         int ok = 0;
         for (int it = 0; it < 2000; ++it, budget *= 1.02) {
@@ -930,29 +1030,31 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
             if (wf > room) wf = room;
             // strip
             P.cone_L0 = T + (int64_t)H * (T - 1);
-            const int can_cone = (D + 1 - P.cone_L0 >= T) && (P.cone_L0 <= BM_CAP);
-            if (D <= BM_CAP && (D <= wm + wm / 2 || !can_cone)) {
+            const int can_cone = (D + 1 - P.cone_L0 >= T) && (P.cone_L0 <= HALF_CAP);
+            if (D <= SPAN_CAP && (D <= wm + wm / 2 || !can_cone)) {
                 P.cone_mode = 0;
                 P.Gs = 1;
                 P.strip_w = D;
             } else if (can_cone) {
                 P.cone_mode = 1;
                 // the strip's first workgroup holds its columns in half its threads
-                const int64_t half = (int64_t)(BM_THREADS / 2) * BM_K;
-                const int64_t ws = wm < half ? wm : half;
+                const int64_t ws = wm < HALF_CAP ? wm : HALF_CAP;
                 int64_t Gs = (D + ws - 1) / ws;
                 if (Gs < 2) Gs = 2;
                 P.strip_w = (D + Gs - 1) / Gs;
                 P.Gs = (int)((D + P.strip_w - 1) / P.strip_w);
                 if (P.strip_w + 1 - P.hmax < T) break;            // halo mirror reads must be older than the block
                 // the strip's first workgroup holds its columns and the cone in one half each
-                if (P.strip_w > (BM_THREADS / 2) * BM_K || P.cone_L0 > (BM_THREADS / 2) * BM_K) break;
-                if (D - (int64_t)(P.Gs - 1) * P.strip_w + P.hmax > BM_CAP) break;
+                if (P.strip_w > HALF_CAP || P.cone_L0 > HALF_CAP) break;
+                if (D - (int64_t)(P.Gs - 1) * P.strip_w + P.hmax > SPAN_CAP) break;
             } else {
                 break;
             }
-            // near part (the first near workgroup needs no halo)
-            int64_t Gn = (near_cols + wm - 1) / wm;
+            // near part (the first near workgroup needs no halo); a near
+            // workgroup spans at most BM_NEAR_CAP columns with its halo
+            int64_t wn = wm;
+            if (wn > BM_NEAR_CAP - (int64_t)P.hmax) wn = BM_NEAR_CAP - (int64_t)P.hmax;
+            int64_t Gn = (near_cols + wn - 1) / wn;
             if (Gn < 1) Gn = 1;
             P.near_w = (near_cols + Gn - 1) / Gn;
             P.Gn = (int)((near_cols + P.near_w - 1) / P.near_w);
