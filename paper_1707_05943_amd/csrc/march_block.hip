@@ -267,6 +267,39 @@ __device__ __forceinline__ cd ld2(const cd* p)
     return mk(x.x, x.y);
 }
 
+// A wave's values of a row written with coalesced stores: lane l holds
+// columns cw + K l .. cw + K l + K-1 (cw: the wave's first column); through
+// the wave's own LDS slot (no barrier: one wave writes and reads it, in
+// order) the wave stores columns cw + 64 i + l, those in [c_lo, c_hi].  The
+// stores go through a buffer resource over the row (row_bytes long): a
+// column outside the range gets an offset past the end, which the hardware
+// drops, so no store sits in a branch.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int RAW_BUFFER_WORD3 = 0x00020000;     // raw (unswizzled, stride 0) buffer, 32-bit data
+constexpr int OUT_OF_RANGE = 0x7ffffff0;
+
+__device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, int row_bytes, int64_t cw,
+                                           int64_t c_lo, int64_t c_hi, int lane)
+{
+    #pragma unroll
+    for (int i = 0; i < K; ++i)
+        *reinterpret_cast<double2*>(slot + K * lane + i) = make_double2(v[i].re, v[i].im);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, row_bytes, RAW_BUFFER_WORD3);
+    u32x4 x[K];
+    #pragma unroll
+    for (int i = 0; i < K; ++i) x[i] = *reinterpret_cast<const u32x4*>(slot + 64 * i + lane);
+    #pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t c = cw + 64 * i + lane;
+        const int off = (c >= c_lo && c <= c_hi) ? (int)(c * 16) : OUT_OF_RANGE;
+        __builtin_amdgcn_raw_buffer_store_b128(x[i], rs, off, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();              // the slot is rewritten by the next row
+}
+
 // The rows of a workgroup whose every column lies beyond 2D: all source
 // terms are exact (tables Et[q] - Et[q+D] and Phi[q] in LDS), the delay rows
 // are the only reads of the ring.  The workgroup's range starts a halo left
@@ -274,7 +307,7 @@ __device__ __forceinline__ cd ld2(const cd* p)
 // carry into its first column is zero.
 __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                          const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
-                                         int64_t rb, int H1, int nst, cd (*dstage)[DSTAGE])
+                                         int64_t rb, int H1, int nst, cd (*dstage)[DSTAGE], cd* wslot)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t D = g.D, C = g.C;
@@ -365,7 +398,6 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         cd cin = prevx;
         if (wv > 0) cmac(cin, lp, wave_tot[par][wv - 1]);
         // the row's values, the ring, P_e
-        char* wp = const_cast<char*>(ring_row(ri.slot)) + own;
         double pe = 0.0;
         up[0] = cin;
         #pragma unroll
@@ -376,12 +408,11 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
             cmac(v, ap[i], cin);
             v = act ? v : zero();
             up[i + 1] = v;
-            if (act && j >= S.own_lo) {
-                *reinterpret_cast<cd*>(wp + 16 * i) = v;
-                const double m2 = norm2(v);
-                pe += (j == g.Nx) ? 0.5 * m2 : m2;
-            }
+            const double m2 = norm2(v);
+            pe += (j < S.own_lo || j > jmax) ? 0.0 : ((j == g.Nx) ? 0.5 * m2 : m2);
         }
+        wave_store(wslot, *reinterpret_cast<const cd(*)[K]>(up + 1), b.ring + (int64_t)uni((int)ri.slot) * C,
+                   (int)(C * 16), j0 - K * lane, S.own_lo, jmax, lane);
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
         if (r + 3 <= rb) fetch(Rn, rinfo[tau + 2].slot_pf);
@@ -771,6 +802,7 @@ __device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64
 struct FarLds {
     cd tab[2][TBL];              // Et[q] - Et[q+D], Phi[q]
     cd dstage[2][DSTAGE];        // delay rows
+    cd wslot[NW][64 * K];        // each wave's row values on their way to coalesced stores
 };
 struct NearLds {
     cd tab[3][TBLN];             // Et[q], Phi[q], Et[q+D]
@@ -917,7 +949,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.lo = P.win_lo;
     W.row0 = ra;
 
-    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage);
+    cd* wslot = sh.u.f.wslot[threadIdx.x >> 6];
+    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage, wslot);
     else if (is_strip)
         strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst, sh.u.s.mstage);
     else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
