@@ -66,6 +66,9 @@ __device__ inline int64_t dec_slot(int64_t s, int64_t R) { return s == 0 ? R - 1
 __device__ inline int64_t inc_slot(int64_t s, int64_t R) { return s + 1 == R ? 0 : s + 1; }
 __device__ inline int64_t slot_or_neg(int64_t rho, int64_t R) { return rho < 0 ? -1 : rho % R; }
 
+// c ? a : b on values (a conditional between two complex lvalues would
+// select their addresses and keep both in scratch memory)
+__device__ __forceinline__ cd csel(bool c, const cd a, const cd b) { return mk(c ? a.re : b.re, c ? a.im : b.im); }
 __device__ inline cd phi_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Phi[q] : zero(); }
 __device__ inline cd et_at(const Bufs& b, int64_t q) { return q >= 0 ? b.Et[q] : zero(); }
 
@@ -418,6 +421,17 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (r + 3 <= rb) fetch(Rn, rinfo[tau + 2].slot_pf);
     };
 
+    // a wave with no column in the range (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
+
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, X, Y);
         if (r + 1 <= rb) step(r + 1, Y, X);
@@ -565,7 +579,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             if (j <= 2 * D) {
                 // second source: -(G/2)[ (m0 + m1)/2 - Et[q+D] half_pr ], with
                 // m0 = psi(0, r-D) exact at j = 2D
-                const cd m0 = (j == 2 * D) ? z0 : mA[i];
+                const cd m0 = csel(j == 2 * D, z0, mA[i]);
                 cmac(v, -c4, (q + D >= 0) ? m0 + mB[i] : zero());
                 cmac(v, -hp, et2);
             } else {
@@ -607,6 +621,17 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         if (r + 3 <= rb) fetch(Rd, Rm, Rc, rinfo[tau + 2].slot_pf, rinfo[tau + 3].slot);
     };
 
+    // a wave with no column in the range (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
+
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, X, Y, MB0, MB1);
         if (r + 1 <= rb) step(r + 1, Y, X, MB1, MB0);
@@ -620,10 +645,11 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
 // psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (its rows staged
 // through LDS) or, for the strip's first columns, from the LDS window of the
 // current block.  The table here starts one entry before q = S.qa + 1.
+template <bool WIN>
 __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw,
                                            cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
                                            const Seg& S, int64_t ra, int64_t rb, int H1, int T, int cone,
-                                           int use_win, int nst, cd (*mstage)[DSTAGE])
+                                           int nst, cd (*mstage)[DSTAGE])
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t D = g.D, C = g.C, Mc = g.Mc;
@@ -722,13 +748,17 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             cmac(v, hp, et);
             cmac(v, drc, pq);
             // bar(D-j, q): the mirror pair, from the window inside the block
-            // (the window is always read, at a valid entry, so that only values are selected)
-            const bool inwin = use_win && cell && q >= W.row0;
-            const int64_t wr = inwin ? q - W.row0 : 0;
-            const int64_t wc = inwin ? D - j - W.lo : 0;
-            const cd w0 = W.w[wr][wc], w1 = W.w[wr][wc + 1];
-            cd m0 = inwin ? ((j < D) ? w0 : zero()) : mA[i];
-            const cd m1 = inwin ? w1 : mB[i];
+            // (the strip's first workgroup reads the window at a valid entry
+            // for every cell, so that only values are selected)
+            cd m0 = mA[i], m1 = mB[i];
+            if constexpr (WIN) {
+                const bool inwin = cell && q >= W.row0;
+                const int64_t wr = inwin ? q - W.row0 : 0;
+                const int64_t wc = inwin ? D - j - W.lo : 0;
+                const cd w0 = W.w[wr][wc], w1 = W.w[wr][wc + 1];
+                m0 = csel(inwin, csel(j < D, w0, zero()), m0);
+                m1 = csel(inwin, w1, m1);
+            }
             if (j == D) m0 = pq * et;                 // psi(0, q)
             cmac(v, c4, (q >= 0) ? m0 + m1 : zero());
             u[i] = cell ? v : zero();
@@ -771,8 +801,20 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
         if (r + 3 <= rb) fetch(Rm, rinfo[tau + 3].slot);
-        if (use_win) __syncthreads();                 // window rows written above are read by the next row
+        if constexpr (WIN) __syncthreads();            // window rows written above are read by the next row
     };
+
+    // a wave with no column in its segment (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+            if constexpr (WIN) __syncthreads();
+        }
+        return;
+    }
 
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, MB0, MB1);
@@ -952,7 +994,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     cd* wslot = sh.u.f.wslot[threadIdx.x >> 6];
     if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage, wslot);
     else if (is_strip)
-        strip_rows(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, use_win, P.nst, sh.u.s.mstage);
+        if (use_win) strip_rows<true>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+        else strip_rows<false>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
     else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
     __syncthreads();
     if (threadIdx.x < nrows) {
