@@ -340,6 +340,18 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         else stage_fetch(R, reinterpret_cast<const cd*>(ring_row(sl)) + d0, 0, nd, wv, lane);
     };
 
+    // a wave with no column in the range (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        __syncthreads();                                      // the prologue's
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
+
     // the base row ra-1 (own columns and the one to the left) and delay row
     // ra-1-D, read directly; stages ra and ra+1 filled, stage ra+2 in flight
     cd up[K + 1], X[K + 1], Y[K + 1], Rn[K];
@@ -421,17 +433,6 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (r + 3 <= rb) fetch(Rn, rinfo[tau + 2].slot_pf);
     };
 
-    // a wave with no column in the range (and no stage entry another wave
-    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
-    // zero P_e parts), leaving its SIMD to the waves that march
-    if (uni((int)(j0 - K * lane > jmax + 1))) {
-        for (int64_t r = ra; r <= rb; ++r) {
-            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
-            __syncthreads();
-        }
-        return;
-    }
-
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, X, Y);
         if (r + 1 <= rb) step(r + 1, Y, X);
@@ -502,6 +503,18 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         stage_put_pad(mstage[par] + K, Pm, nm, wv, lane);
         dstage[par][NCARRY + lane] = Pc;
     };
+
+    // a wave with no column in the range (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        __syncthreads();                                      // the prologue's
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
 
     // base row ra-1, delay row ra-1-D and the second mirror values of row ra
     // (Md row of diagonal ra-1-D) read directly; stages ra, ra+1 filled,
@@ -621,17 +634,6 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         if (r + 3 <= rb) fetch(Rd, Rm, Rc, rinfo[tau + 2].slot_pf, rinfo[tau + 3].slot);
     };
 
-    // a wave with no column in the range (and no stage entry another wave
-    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
-    // zero P_e parts), leaving its SIMD to the waves that march
-    if (uni((int)(j0 - K * lane > jmax + 1))) {
-        for (int64_t r = ra; r <= rb; ++r) {
-            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
-            __syncthreads();
-        }
-        return;
-    }
-
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, X, Y, MB0, MB1);
         if (r + 1 <= rb) step(r + 1, Y, X, MB1, MB0);
@@ -682,6 +684,18 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         stage_fetch(R, b.Md + (int64_t)uni((int)sl) * Mc + cm, mlo, nm, sv, lane);
     };
 
+    // a wave with no column in the range (and no stage entry another wave
+    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
+    // zero P_e parts), leaving its SIMD to the waves that march
+    if (uni((int)(j0 - K * lane > jmax + 1))) {
+        __syncthreads();                                      // the prologue's
+        for (int64_t r = ra; r <= rb; ++r) {
+            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
+            __syncthreads();
+        }
+        return;
+    }
+
     // base row ra-1 and the second mirror values of row ra (Md row of
     // diagonal ra-1-D) read directly; stages ra, ra+1 filled, ra+2 in flight
     cd up[K + 1];
@@ -716,7 +730,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
         int64_t act_lo = S.trap ? S.lo + (int64_t)H1 * tau : S.lo;
-        if (cone && tid >= NT / 2 && tau > T - 2) act_lo = S.hi;        // the cone stops a row early
+        if (cone && S.t0 != 0 && tau > T - 2) act_lo = S.hi;            // the cone stops a row early
         cd mA[K];
         {
             cd V[K + 1];
@@ -749,15 +763,19 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             cmac(v, drc, pq);
             // bar(D-j, q): the mirror pair, from the window inside the block
             // (the strip's first workgroup reads the window at a valid entry
-            // for every cell, so that only values are selected)
+            // for every cell, so that only values are selected).  The pair of
+            // column 1, psi(D-1, r-1) and psi(D, r-1), is written after the
+            // previous row's barrier: its term is added after this row's
+            // barrier instead (see below).
             cd m0 = mA[i], m1 = mB[i];
             if constexpr (WIN) {
                 const bool inwin = cell && q >= W.row0;
+                const bool late = (j == 1);
                 const int64_t wr = inwin ? q - W.row0 : 0;
                 const int64_t wc = inwin ? D - j - W.lo : 0;
                 const cd w0 = W.w[wr][wc], w1 = W.w[wr][wc + 1];
-                m0 = csel(inwin, csel(j < D, w0, zero()), m0);
-                m1 = csel(inwin, w1, m1);
+                m0 = csel(inwin, csel(j < D && !late, w0, zero()), m0);
+                m1 = csel(inwin, csel(!late, w1, zero()), m1);
             }
             if (j == D) m0 = pq * et;                 // psi(0, q)
             cmac(v, c4, (q >= 0) ? m0 + m1 : zero());
@@ -776,18 +794,38 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         cd cin = prevx;
         if (wv > S.w0) cmac(cin, lp, wave_tot[par][wv - 1]);
         if (first) cin = S.exact ? ri.psi0 : zero();
+        // the late term of column 1: c4 (psi(D-1, r-1) + psi(D, r-1)) enters
+        // column j as alpha^(j-1) times itself (the recurrence is linear), the
+        // carry cin (column j0-1) included; past the first wave of the
+        // segment its weight is below alpha^(64K)
+        cd late = zero(), latep = zero();
+        if constexpr (WIN) {
+            if (S.use_win && wv == S.w0 && r - 1 >= W.row0) {
+                const cd* wl = W.w[r - 1 - W.row0];
+                const cd pd = wl[D - W.lo];
+                const cd pd1 = wl[D > 1 ? D - 1 - W.lo : D - W.lo];
+                const cd dl = c4 * (D > 1 ? pd1 + pd : pd);
+                late = lp * dl;
+                latep = (pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1]) * dl;
+                latep = csel(lane > 0, latep, zero());
+            }
+        }
         // outputs
         cd* rowp = b.ring + (int64_t)uni((int)ri.slot) * C;
         double pe = 0.0;
         int64_t sd = sdr;
         sdr = inc_slot(sdr, R);
-        up[0] = cin;
+        up[0] = cin + latep;
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t j = j0 + i;
             const bool act = (j >= act_lo && j <= jmax);
             cd v = u[i];
             cmac(v, ap[i], cin);
+            if constexpr (WIN) {
+                v = v + late;
+                late = late * al;
+            }
             v = act ? v : zero();
             up[i + 1] = v;
             if (act && j >= S.own_lo) {
@@ -801,20 +839,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
         if (r + 3 <= rb) fetch(Rm, rinfo[tau + 3].slot);
-        if constexpr (WIN) __syncthreads();            // window rows written above are read by the next row
     };
-
-    // a wave with no column in its segment (and no stage entry another wave
-    // reads: entry jmax-lo+1 is the last) only keeps the barrier count (and
-    // zero P_e parts), leaving its SIMD to the waves that march
-    if (uni((int)(j0 - K * lane > jmax + 1))) {
-        for (int64_t r = ra; r <= rb; ++r) {
-            if (lane == 63) pe_lds[r - ra][wv] = 0.0;
-            __syncthreads();
-            if constexpr (WIN) __syncthreads();
-        }
-        return;
-    }
 
     for (int64_t r = ra; r <= rb; r += 2) {
         step(r, MB0, MB1);
@@ -931,9 +956,18 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     S.tE = tab0;
     S.tP = tab1;
     S.tE2 = tab2;
-    if (cone && threadIdx.x >= NT / 2) {
-        S.t0 = NT / 2;
-        S.w0 = NW / 2;
+    // The cone's waves follow the strip half's marching waves on the SIMDs
+    // (wave w runs on SIMD w mod 4) when both fit in four: waves of the
+    // second half before the cone are idle members of the strip half.
+    int cone_w0 = NW / 2;
+    if (cone) {
+        const int a = (int)(((P.strip_w + K - 1) / K + 63) / 64);
+        const int bw = (int)(((P.cone_L0 + K - 1) / K + 63) / 64);
+        cone_w0 = NW / 2 + a < NW - bw ? NW / 2 + a : NW - bw;
+    }
+    if (cone && (int)threadIdx.x >= 64 * cone_w0) {
+        S.t0 = 64 * cone_w0;
+        S.w0 = cone_w0;
         S.lo = D + 1 - P.cone_L0;
         S.hi = D + 1;
         S.own_lo = D + 1;                        // nothing owned: the cone only fills the window
