@@ -397,7 +397,11 @@ int launch_boundary(fdtd_ctx* c, int from_host_E)
 
 int launch_clear(fdtd_ctx* c)
 {
+    // the ring and the diagonal copy start at zero: rows before t = 0 are
+    // read (and their terms dropped) before they are first written
     const int64_t n = c->g.R * c->g.C;
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, n);
+    const int64_t nm = c->g.R * c->g.Mc;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((nm + 255) / 256)), dim3(256), 0, c->stream, c->b.Md, nm);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
