@@ -667,6 +667,11 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const cd* tE = S.tE;
     const cd* tP = S.tP;
     const bool first = (tid == S.t0);
+    // the window's column offset, and alpha^(K lane - 1) (lanes >= 1): the
+    // weight of the late column-1 term in the carried value of column j0-1
+    const int dwl = (int)(D - W.lo);
+    cd lpm = zero();
+    if constexpr (WIN) lpm = csel(lane > 0, pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1], zero());
 
     // stage rho: the Md row of diagonal rho - D, entry s is its column
     // cm + s (cm = D - jmax), stored K entries in, each segment in its own
@@ -769,11 +774,13 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             // barrier instead (see below).
             cd m0 = mA[i], m1 = mB[i];
             if constexpr (WIN) {
-                const bool inwin = cell && q >= W.row0;
-                const bool late = (j == 1);
-                const int64_t wr = inwin ? q - W.row0 : 0;
-                const int64_t wc = inwin ? D - j - W.lo : 0;
-                const cd w0 = W.w[wr][wc], w1 = W.w[wr][wc + 1];
+                // window row q - ra = tau - j, column D - j - W.lo (32-bit: j < NT K)
+                const int jj = (int)j;
+                const int wr = tau - jj;
+                const bool inwin = cell && wr >= 0;
+                const bool late = (jj == 1);
+                const cd* wp = &W.w[0][0] + (inwin ? wr * BM_TMAX + (dwl - jj) : 0);
+                const cd w0 = wp[0], w1 = wp[1];
                 m0 = csel(inwin, csel(j < D && !late, w0, zero()), m0);
                 m1 = csel(inwin, csel(!late, w1, zero()), m1);
             }
@@ -800,14 +807,12 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         // segment its weight is below alpha^(64K)
         cd late = zero(), latep = zero();
         if constexpr (WIN) {
-            if (S.use_win && wv == S.w0 && r - 1 >= W.row0) {
-                const cd* wl = W.w[r - 1 - W.row0];
-                const cd pd = wl[D - W.lo];
-                const cd pd1 = wl[D > 1 ? D - 1 - W.lo : D - W.lo];
-                const cd dl = c4 * (D > 1 ? pd1 + pd : pd);
+            if (S.use_win && wv == S.w0 && tau >= 1) {
+                const cd* wl = W.w[tau - 1] + dwl;
+                const cd pd = wl[0];
+                const cd dl = c4 * (D > 1 ? wl[-1] + pd : pd);
                 late = lp * dl;
-                latep = (pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1]) * dl;
-                latep = csel(lane > 0, latep, zero());
+                latep = lpm * dl;
             }
         }
         // outputs
