@@ -319,10 +319,8 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     const bool live = j0 <= jmax;
     const unsigned own = (unsigned)(j0 * 16);                 // byte offset of column j0 in a row
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
-    cd ap[K];                                                 // alpha^(i+1)
-    #pragma unroll
-    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
-    const cd lp = pw.lp[lane];
+    cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
+                                                              // prologue's barrier (the set-up writes them)
     const cd* tE = S.tE;
     const cd* tP = S.tP;
 
@@ -369,12 +367,15 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         if (uni((int)sx) < 0) stage_zero(X);
         cd R0[K], R1[K];
         fetch(R0, slot_or_neg(ra - D, g.R));
-        if (ra + 1 <= rb) fetch(R1, rinfo[0].slot_pf);
+        if (ra + 1 <= rb) fetch(R1, slot_or_neg(ra + 1 - D, g.R));
         stage_put(dstage[0], R0, wv, lane);
         if (ra + 1 <= rb) stage_put(dstage[1], R1, wv, lane);
-        if (ra + 2 <= rb) fetch(Rn, rinfo[1].slot_pf);
+        if (ra + 2 <= rb) fetch(Rn, slot_or_neg(ra + 2 - D, g.R));
     }
-    __syncthreads();
+    __syncthreads();                                          // also publishes the set-up (tables, rows, powers)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
+    lp = pw.lp[lane];
 
     // row r: A holds delay row r-1-D, Bv receives row r-D from stage r
     auto step = [&](int64_t r, const cd (&A)[K + 1], cd (&Bv)[K + 1]) __attribute__((always_inline)) {
@@ -458,10 +459,8 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     const unsigned own = (unsigned)(j0 * 16);
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
-    cd ap[K];                                                 // alpha^(i+1)
-    #pragma unroll
-    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
-    const cd lp = pw.lp[lane];
+    cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
+                                                              // prologue's barrier (the set-up writes them)
     const cd* tE = S.tE;
     const cd* tP = S.tP;
     const cd* tE2 = S.tE2;
@@ -525,7 +524,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
         const char* rp = ring_row((ra - 1) % g.R) + own;
         const int64_t sx = slot_or_neg(ra - 1 - D, g.R);
         const cd* xp = reinterpret_cast<const cd*>(ring_row(sx < 0 ? 0 : sx)) + d0;
-        const cd* mp = b.Md + (int64_t)uni((int)rinfo[0].slot_m1) * Mc + cm;
+        const cd* mp = b.Md + (int64_t)uni((int)((ra - 1) % g.R)) * Mc + cm;
         #pragma unroll
         for (int i = 0; i <= K; ++i) {
             const int64_t j = j0 - 1 + i;
@@ -541,13 +540,16 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             MB0[i] = ld2(mp + e);
         }
         cd P0[K], P1[K], M0[K], M1[K], c0, c1;
-        fetch(P0, M0, c0, slot_or_neg(ra - D, g.R), rinfo[0].slot);
-        if (ra + 1 <= rb) fetch(P1, M1, c1, rinfo[0].slot_pf, rinfo[1].slot);
+        fetch(P0, M0, c0, slot_or_neg(ra - D, g.R), ra % g.R);
+        if (ra + 1 <= rb) fetch(P1, M1, c1, slot_or_neg(ra + 1 - D, g.R), (ra + 1) % g.R);
         put(0, P0, M0, c0);
         if (ra + 1 <= rb) put(1, P1, M1, c1);
-        if (ra + 2 <= rb) fetch(Rd, Rm, Rc, rinfo[1].slot_pf, rinfo[2].slot);
+        if (ra + 2 <= rb) fetch(Rd, Rm, Rc, slot_or_neg(ra + 2 - D, g.R), (ra + 2) % g.R);
     }
-    __syncthreads();
+    __syncthreads();                                          // also publishes the set-up (tables, rows, powers)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
+    lp = pw.lp[lane];
 
     // row r: A holds delay row r-1-D, Bv receives row r-D; mB holds the
     // second mirror values of row r, mBn receives those of row r+1
@@ -660,10 +662,8 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const bool live = j0 <= jmax;
     const cd al = g.alpha, cA = g.cA, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
-    cd ap[K];                                                 // alpha^(i+1)
-    #pragma unroll
-    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
-    const cd lp = pw.lp[lane];
+    cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
+                                                              // prologue's barrier (the set-up writes them)
     const cd* tE = S.tE;
     const cd* tP = S.tP;
     const bool first = (tid == S.t0);
@@ -671,7 +671,6 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     // weight of the late column-1 term in the carried value of column j0-1
     const int dwl = (int)(D - W.lo);
     cd lpm = zero();
-    if constexpr (WIN) lpm = csel(lane > 0, pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1], zero());
 
     // stage rho: the Md row of diagonal rho - D, entry s is its column
     // cm + s (cm = D - jmax), stored K entries in, each segment in its own
@@ -712,7 +711,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             const int64_t j = j0 - 1 + i;
             up[i] = (live && j <= jmax) ? (j >= 1 ? rp[j] : phi_at(b, ra - 1) * et_at(b, ra - 1)) : zero();
         }
-        const cd* mp = b.Md + (int64_t)uni((int)rinfo[0].slot_m1) * Mc + cm;
+        const cd* mp = b.Md + (int64_t)uni((int)((ra - 1) % g.R)) * Mc + cm;
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             int64_t e = em - soff + (K - i);                  // entry jmax - j0 - i + 1
@@ -720,13 +719,17 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             MB0[i] = ld2(mp + e);
         }
         cd P0[K], P1[K];
-        fetch(P0, rinfo[0].slot);
-        if (ra + 1 <= rb) fetch(P1, rinfo[1].slot);
+        fetch(P0, ra % g.R);
+        if (ra + 1 <= rb) fetch(P1, (ra + 1) % g.R);
         stage_put(mstage[0] + soff, P0, sv, lane);
         if (ra + 1 <= rb) stage_put(mstage[1] + soff, P1, sv, lane);
-        if (ra + 2 <= rb) fetch(Rm, rinfo[2].slot);
+        if (ra + 2 <= rb) fetch(Rm, (ra + 2) % g.R);
     }
-    __syncthreads();
+    __syncthreads();                                          // also publishes the set-up (tables, rows, powers)
+    #pragma unroll
+    for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
+    lp = pw.lp[lane];
+    if constexpr (WIN) lpm = csel(lane > 0, pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1], zero());
     const int64_t R = g.R;
     int64_t sdr = ((ra - j0 + D) % R + R) % R;                  // Md row of diagonal r - j0, row by row
 
@@ -1023,7 +1026,8 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     } else {
         fill_tables(b, D, far, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab0, tab1, far ? nullptr : tab2, 0, NT);
     }
-    __syncthreads();
+    // no barrier here: the row loops' prologues issue their loads first and
+    // their barrier publishes these tables, rows and powers as well
 
     Win W;
     W.w = sh.u.s.win;
