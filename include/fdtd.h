@@ -144,6 +144,20 @@ enum fdtd_readout_kind {
  * waits for the stream).  Complex outputs are (re, im) pairs. */
 int fdtd_readout(fdtd_ctx *ctx, int32_t what, int64_t arg, void *dst, int64_t count, int32_t dst_on_device);
 
+/* Checkpoint and restore of a march (its state is the workspace: the ring
+ * of the last D+2T+2 rows, the diagonal copy of the strip, the boundary
+ * tables and the per-row sums of |psi|^2, plus the row counters).
+ * fdtd_checkpoint_size gives the bytes a checkpoint takes; fdtd_checkpoint
+ * waits for the context's stream and copies the state into the caller's
+ * host buffer h_dst (at least that many bytes); fdtd_restore copies a
+ * checkpoint into a context made with the same parameters (another
+ * workspace is fine) and sets its rows, so that marching on gives the same
+ * values bit for bit.  Errors: FDTD_EINVAL (NULL, not a checkpoint, other
+ * parameters), FDTD_ESIZE (buffer too small or truncated), FDTD_EDEVICE. */
+int fdtd_checkpoint_size(const fdtd_ctx *ctx, size_t *bytes);
+int fdtd_checkpoint(fdtd_ctx *ctx, void *h_dst, size_t bytes);
+int fdtd_restore(fdtd_ctx *ctx, const void *h_src, size_t bytes);
+
 /* Wait for all work of this context. */
 int fdtd_sync(fdtd_ctx *ctx);
 

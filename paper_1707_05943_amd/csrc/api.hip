@@ -456,6 +456,77 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
     return FDTD_OK;
 }
 
+// checkpoint: a header, then the context's workspace (ring, diagonal copy,
+// tables, partial sums) byte for byte
+static int64_t ws_bytes(const fdtd_ctx* c) { return layout(&c->p, c->plan).total; }
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    fdtd_params p;
+    int64_t row, strip_row, boundary_ready, ws_bytes;
+};
+static const char CKPT_MAGIC[8] = {'F', 'D', 'T', 'D', 'C', 'K', 'P', '1'};
+
+int fdtd_checkpoint_size(const fdtd_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return FDTD_EINVAL;
+    *bytes = sizeof(CkptHeader) + (size_t)ws_bytes(c);
+    return FDTD_OK;
+}
+
+int fdtd_checkpoint(fdtd_ctx* c, void* h_dst, size_t bytes)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    if (!h_dst) return fail(c, FDTD_EINVAL, "destination is NULL");
+    const size_t need = sizeof(CkptHeader) + (size_t)ws_bytes(c);
+    if (bytes < need) return fail(c, FDTD_ESIZE, "checkpoint needs %zu bytes", need);
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, CKPT_MAGIC, sizeof h.magic);
+    h.version = 1;
+    h.header_bytes = (uint32_t)sizeof h;
+    h.p = c->p;
+    h.row = c->row;
+    h.strip_row = c->strip_row;
+    h.boundary_ready = c->boundary_ready;
+    h.ws_bytes = ws_bytes(c);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)h_dst + sizeof h, c->b.ring, (size_t)ws_bytes(c), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "checkpoint copy failed: %s", hipGetErrorString(e));
+    memcpy(h_dst, &h, sizeof h);
+    return FDTD_OK;
+}
+
+int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
+{
+    if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
+    if (!h_src || bytes < sizeof(CkptHeader)) return fail(c, FDTD_EINVAL, "not a checkpoint");
+    CkptHeader h;
+    memcpy(&h, h_src, sizeof h);
+    if (memcmp(h.magic, CKPT_MAGIC, sizeof h.magic) || h.version != 1 || h.header_bytes != sizeof h)
+        return fail(c, FDTD_EINVAL, "not a checkpoint of this library");
+    if (memcmp(&h.p, &c->p, sizeof h.p) || h.ws_bytes != ws_bytes(c))
+        return fail(c, FDTD_EINVAL, "checkpoint of other parameters");
+    if (bytes < sizeof h + (size_t)h.ws_bytes) return fail(c, FDTD_ESIZE, "checkpoint is truncated");
+    hipError_t e = hipMemcpyAsync(c->b.ring, (const char*)h_src + sizeof h, (size_t)h.ws_bytes,
+                                  hipMemcpyHostToDevice, c->stream);
+    // the delay-equation launch record holds this context's device pointers
+    OdeInst oi;
+    memset(&oi, 0, sizeof oi);
+    oi.g = c->g;
+    oi.pk = c->pk;
+    oi.b = c->b;
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_ode, &oi, sizeof oi, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "restore copy failed: %s", hipGetErrorString(e));
+    c->row = h.row;
+    c->strip_row = h.strip_row;
+    c->boundary_ready = (int)h.boundary_ready;
+    return FDTD_OK;
+}
+
 int fdtd_sync(fdtd_ctx* c)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");

@@ -25,6 +25,7 @@ STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", 
 # every symbol include/fdtd.h declares
 EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_boundary_tables",
            "fdtd_march", "fdtd_current_row", "fdtd_readout", "fdtd_sync", "fdtd_destroy",
+           "fdtd_checkpoint_size", "fdtd_checkpoint", "fdtd_restore",
            "fdtd_describe", "fdtd_strerror", "fdtd_last_error",
            "fdtd_batch_workspace_size", "fdtd_batch_init", "fdtd_batch_set_boundary", "fdtd_batch_march",
            "fdtd_batch_readout", "fdtd_batch_info", "fdtd_batch_sync", "fdtd_batch_destroy",
@@ -77,6 +78,9 @@ def load(path: str = LIB_PATH):
     lib.fdtd_current_row.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fdtd_readout.argtypes = [vp, i32, i64, vp, i64, i32]
     lib.fdtd_sync.argtypes = [vp]
+    lib.fdtd_checkpoint_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fdtd_checkpoint.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.fdtd_restore.argtypes = [vp, vp, ctypes.c_size_t]
     lib.fdtd_destroy.argtypes = [vp]
     lib.fdtd_describe.argtypes = [P, ctypes.c_char_p, ctypes.c_size_t]
     lib.fdtd_strerror.argtypes = [ctypes.c_int]
@@ -181,6 +185,19 @@ class Solver:
         self._check(self.lib.fdtd_readout(self.ctx, what, int(arg), out.ctypes.data_as(ctypes.c_void_p),
                                           int(count), 0))
         return out
+
+    def checkpoint(self) -> np.ndarray:
+        """the march's state as bytes (host memory)"""
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.fdtd_checkpoint_size(self.ctx, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(self.lib.fdtd_checkpoint(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        return buf
+
+    def restore(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(self.lib.fdtd_restore(self.ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.size))
+        return self
 
     def row_values(self, rho: int) -> np.ndarray:
         return self._ro(RO_ROW, rho, self.p.Nx + 1, np.complex128)

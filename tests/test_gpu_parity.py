@@ -232,6 +232,40 @@ def test_resume_is_bitwise():
     assert np.array_equal(a.pe(), b.pe())
 
 
+@pytest.mark.parametrize("name", ["gauss_D10_Nx2600", "gauss_D1200_Nx3100"])
+def test_checkpoint_restore_is_bitwise(name):
+    """A march checkpointed at row 117 and restored into a fresh context (its
+    own workspace), or into the same context after it marched on, continues
+    to the same values bit for bit."""
+    inst = MARCH_CASES[name]
+    _say(f"[parity] checkpoint/restore: {name}")
+    E = oracle.E_table(inst)
+    a = fdtd.Solver(inst).set_boundary(E)
+    a.march(inst.Nt)
+    b = fdtd.Solver(inst).set_boundary(E)
+    b.march(117)
+    ck = b.checkpoint()
+    b.march(inst.Nt - 117)
+    c = fdtd.Solver(inst).set_boundary(E)
+    c.restore(ck)
+    assert c.row == 117
+    c.march(inst.Nt - 117)
+    b.restore(ck)
+    b.march(inst.Nt - 117)
+    for s in (b, c):
+        for rho in range(inst.Nt - inst.D - 1, inst.Nt + 1):
+            assert np.array_equal(a.row_values(rho), s.row_values(rho))
+        assert np.array_equal(a.pe(), s.pe())
+    # a checkpoint of other parameters, and a truncated one, are refused
+    other = fdtd.Solver(MARCH_CASES["gauss_D40_Nx1025"]).set_boundary()
+    with pytest.raises(fdtd.FdtdError) as e:
+        other.restore(ck)
+    assert e.value.code == -1
+    with pytest.raises(fdtd.FdtdError) as e:
+        c.restore(ck[: ck.size // 2])
+    assert e.value.code == -2
+
+
 def test_state_errors():
     inst = MARCH_CASES["gauss_D2_min"]
     sol = fdtd.Solver(inst)
