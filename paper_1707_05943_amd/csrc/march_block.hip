@@ -683,7 +683,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const int64_t nm = jmax - S.lo + 1;
     const int64_t mlo = cm < 1 ? 1 - cm : 0;
     const int em = soff + (live ? (int)(jmax - j0) - (K - 1) : 0);
-    cd Rm[K];
+    cd RmA[K], RmB[K];                                        // stages of even / odd rows, two rows ahead
     auto fetch = [&](cd (&R)[K], int64_t sl) __attribute__((always_inline)) {
         stage_fetch(R, b.Md + (int64_t)uni((int)sl) * Mc + cm, mlo, nm, sv, lane);
     };
@@ -723,7 +723,8 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         if (ra + 1 <= rb) fetch(P1, (ra + 1) % g.R);
         stage_put(mstage[0] + soff, P0, sv, lane);
         if (ra + 1 <= rb) stage_put(mstage[1] + soff, P1, sv, lane);
-        if (ra + 2 <= rb) fetch(Rm, (ra + 2) % g.R);
+        if (ra + 2 <= rb) fetch(RmA, (ra + 2) % g.R);
+        if (ra + 3 <= rb) fetch(RmB, (ra + 3) % g.R);
     }
     __syncthreads();                                          // also publishes the set-up (tables, rows, powers)
     #pragma unroll
@@ -733,7 +734,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const int64_t R = g.R;
     int64_t sdr = ((ra - j0 + D) % R + R) % R;                  // Md row of diagonal r - j0, row by row
 
-    auto step = [&](int64_t r, const cd (&mB)[K], cd (&mBn)[K]) __attribute__((always_inline)) {
+    auto step = [&](int64_t r, const cd (&mB)[K], cd (&mBn)[K], cd (&Rm)[K]) __attribute__((always_inline)) {
         const int tau = (int)(r - ra);
         const int par = tau & 1;
         const RowInfo& ri = rinfo[tau];
@@ -846,12 +847,12 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         }
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
-        if (r + 3 <= rb) fetch(Rm, rinfo[tau + 3].slot);
+        if (r + 4 <= rb) fetch(Rm, rinfo[tau + 4].slot);
     };
 
     for (int64_t r = ra; r <= rb; r += 2) {
-        step(r, MB0, MB1);
-        if (r + 1 <= rb) step(r + 1, MB1, MB0);
+        step(r, MB0, MB1, RmA);
+        if (r + 1 <= rb) step(r + 1, MB1, MB0, RmB);
     }
 }
 
