@@ -85,6 +85,36 @@ def large_gauss(seed: int = 2) -> Instance:
                              k0a=0.5 * math.pi, width=1.0, Nx=262144, Nt=131072, seed=seed)
 
 
+def paper_sets() -> dict:
+    """The parameter sets of the paper's validation figures: a two-photon plane
+    wave (identical photons, Eqs. 5-6) in the paper's absolute units, Ny = Nt + 1.
+    * the error snapshots: nx = 200, Nx = 4000, Ny = 4e4, Delta = 1e-2,
+      k = omega0 = pi/2, Gamma = pi/40;
+    * |chi|^2 at k0 a = pi/4: nx = 50, Nx = 1e4, Ny = 2.5e4, Delta = 1e-2,
+      omega0 = pi, Gamma = pi/20, with k = omega0 and k = omega0 - Gamma;
+    * |chi|^2 at k0 a = pi/2: nx = 200, Nx = 1e4, Ny = 2e4, Delta = 1e-2,
+      omega0 = pi/2, Gamma = pi/40, with k = omega0 and k = omega0 - Gamma;
+    * the strongly non-Markovian cases k0 a = 10.5 pi and 20.5 pi: Nx = 64800,
+      Ny = 6e4, Delta = pi/12000, k = omega0 = 100, Gamma = 1 (nx = 2a/Delta =
+      2520 and 4920)."""
+    def plane(name, D, Nx, Ny, Delta, omega0, Gamma, k):
+        return Instance(name=name, Nx=int(Nx), D=int(D), Nt=int(Ny) - 1, Delta=float(Delta),
+                        omega0=float(omega0), Gamma=float(Gamma), incident=INC_PLANE, k=float(k))
+    pi = math.pi
+    out = {}
+    for inst in (
+        plane("paper_error_snapshots", 200, 4000, 40000, 1e-2, pi / 2, pi / 40, pi / 2),
+        plane("paper_chi_k0a_pi4_res", 50, 10000, 25000, 1e-2, pi, pi / 20, pi),
+        plane("paper_chi_k0a_pi4_det", 50, 10000, 25000, 1e-2, pi, pi / 20, pi - pi / 20),
+        plane("paper_chi_k0a_pi2_res", 200, 10000, 20000, 1e-2, pi / 2, pi / 40, pi / 2),
+        plane("paper_chi_k0a_pi2_det", 200, 10000, 20000, 1e-2, pi / 2, pi / 40, pi / 2 - pi / 40),
+        plane("paper_chi_nonmarkov_10.5pi", 2520, 64800, 60000, pi / 12000, 100.0, 1.0, 100.0),
+        plane("paper_chi_nonmarkov_20.5pi", 4920, 64800, 60000, pi / 12000, 100.0, 1.0, 100.0),
+    ):
+        out[inst.name] = inst
+    return out
+
+
 def with_sizes(inst: Instance, *, Nx: int | None = None, Nt: int | None = None,
                name: str | None = None) -> Instance:
     """Same physics and grid step, other box sizes (a column window or a row prefix)."""

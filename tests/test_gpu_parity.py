@@ -219,6 +219,30 @@ def test_large_gauss_column_window():
     sol.close()
 
 
+@pytest.mark.parametrize("name", list(W.paper_sets()))
+def test_paper_parameter_sets_column_window(name):
+    """The paper's validation parameter sets (plane wave; the error snapshots,
+    the chi comparisons at k0 a = pi/4, pi/2 and the non-Markovian ones)
+    marched at full width for D+400 rows: by chirality the oracle on the
+    first 2D+600 columns reproduces those columns."""
+    inst = W.paper_sets()[name]
+    rows = min(inst.Nt, inst.D + 400)
+    gpu_inst = W.with_sizes(inst, Nt=rows)
+    win = W.with_sizes(inst, Nx=min(inst.Nx, 2 * inst.D + 600), Nt=rows)
+    _say(f"[parity] paper set {name}: D={inst.D} Nx={inst.Nx} rows={rows} window={win.Nx}")
+    E = oracle.E_table(win)
+    ref = oracle.march(win, E)
+    sol = fdtd.Solver(gpu_inst).set_boundary()
+    sol.march(rows)
+    scale = max(np.linalg.norm(v) for v in ref["ring"])
+    for q in (0, 1, win.D // 2, win.D, win.D + 1):
+        rho = rows - (win.D + 1) + q
+        got = sol.row_values(rho)[: win.Nx + 1]
+        e = _row_err(got, ref["ring"][q], scale)
+        assert e <= TOL, ("row", rho, e)
+    sol.close()
+
+
 def test_resume_is_bitwise():
     inst = MARCH_CASES["gauss_D10_Nx2600"]
     E = oracle.E_table(inst)
