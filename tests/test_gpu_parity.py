@@ -243,6 +243,29 @@ def test_paper_parameter_sets_column_window(name):
     sol.close()
 
 
+@pytest.mark.parametrize("name", ["paper_chi_k0a_pi2_res", "paper_chi_k0a_pi4_det"])
+def test_paper_g2_reaches_steady_state(name):
+    """g2(tau) = |chi(a + Delta, a + Delta + tau, t)|^2 is defined in the long-time
+    limit; with no scattering-theory data at hand the check is that limit:
+    over the last 40 time units (t Gamma from 12 to 16 at k0 a = pi/2, from
+    10 to 12 at pi/4) the profile settles, each 20-unit change below 1e-4 of
+    the profile and smaller than the one before."""
+    inst = W.paper_sets()[name]
+    _say(f"[parity] g2 steady state: {name}")
+    sol = fdtd.Solver(inst).set_boundary()
+    n = 2000
+    prof = []
+    for r in (inst.Nt - 4000, inst.Nt - 2000, inst.Nt):
+        sol.march(r - sol.row)
+        prof.append(np.abs(sol.chi(n)) ** 2)
+    d1 = np.linalg.norm(prof[1] - prof[0]) / np.linalg.norm(prof[2])
+    d2 = np.linalg.norm(prof[2] - prof[1]) / np.linalg.norm(prof[2])
+    _say(f"[parity] {name}: relative changes {d1:.2e} then {d2:.2e}")
+    assert np.all(np.isfinite(prof[2])) and prof[2].max() > 0
+    assert d1 < 1e-4 and d2 < 1e-4 and d2 < d1
+    sol.close()
+
+
 def test_resume_is_bitwise():
     inst = MARCH_CASES["gauss_D10_Nx2600"]
     E = oracle.E_table(inst)
