@@ -17,6 +17,8 @@ Parity status of each part (what pins it, see tests/test_oracle_*.py):
     turn converges to the exact solution in x <= -a (paper's test 1) and
     conserves the two-excitation probability as Delta -> 0
   * chi readout, Eq. (2)       -- the micro-oracle's full-grid Eq. (2)
+  * mu, lambda, App. D (nm.py) -- conservation of the one-excitation sector,
+    the exact value at t = 0, the uncoupled limit
 """
 from __future__ import annotations
 
