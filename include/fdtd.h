@@ -135,8 +135,18 @@ enum fdtd_readout_kind {
                           the exact part x <= -a plus the trapezoid rule over columns 0..Nx */
     FDTD_RO_CHI = 3,   /* chi(x1, x2, t) of Eq. (2) at the current row, detectors x1 = a + Delta,
                           x2 = x1 + k Delta for k = 0..count-1 (count <= Nx-D) */
-    FDTD_RO_E = 4      /* the boundary table c E(t_r), r = 0..count-1 (count <= Nt+1); c = sqrt(2) e^{i theta}
+    FDTD_RO_E = 4,     /* the boundary table c E(t_r), r = 0..count-1 (count <= Nt+1); c = sqrt(2) e^{i theta}
                           for two photons, 1 for stimulated emission */
+    /* Non-Markovian measures of stimulated emission (App. D; FDTD_INC_EXP1 contexts only, else
+       FDTD_EINVAL).  e0(t) is the emitter amplitude of the one-excitation problem with the same
+       packet and the emitter initially in its ground state, phi(x,t) = phi_in(x-t)
+       - sqrt(G/2) e0(t-(x+a)) [x > -a] + sqrt(G/2) e0(t-(x-a)) [x > a] its photon field.
+       Quadrature as for FDTD_RO_PE. */
+    FDTD_RO_MU = 5,    /* mu(t_r) = int phi*(x,t_r) psi(x,t_r) dx for r = 0..count-1, complex; accumulated row
+                          by row by fdtd_march (count <= current+1; instances of a batch hold row 0 only,
+                          FDTD_ESTATE beyond) */
+    FDTD_RO_LAMBDA = 6 /* lambda(t_r) = int |psi(x,t_r)|^2 dx - |e0(t_r)|^2 for r = 0..count-1 (count <= current+1),
+                          doubles; the determinant of the dynamical map is |mu|^2 lambda */
 };
 
 /* Copy a readout into dst: a device pointer (dst_on_device = 1, enqueued on

@@ -94,7 +94,7 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
 static int validate(const fdtd_params* p, char* why, size_t n) { return ctx_validate(p, SOLO_KNOBS, why, n); }
 
 struct Layout {
-    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, Epart, total;
+    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, Epart, E0, Mu, mupart, total;
 };
 
 // ring rows: the delay reaches D+1 rows back; the strip runs one block of T
@@ -125,6 +125,13 @@ static Layout layout(const fdtd_params* p, const Plan& P)
     if (p->incident == FDTD_INC_GAUSS2 && p->boundary == FDTD_E_SERIES) {
         L.Epart = off;
         off += align256((int64_t)EPART_CHUNKS * n * 16);
+    }
+    // stimulated emission: e0, mu and mu's per-row partial sums (App. D)
+    L.E0 = L.Mu = L.mupart = -1;
+    if (p->incident == FDTD_INC_EXP1) {
+        L.E0 = off; off += align256(n * 16);
+        L.Mu = off; off += align256(n * 16);
+        L.mupart = off; off += align256(n * NM_BLOCKS * 16);
     }
     L.total = off;
     return L;
@@ -252,6 +259,10 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     b.ode = (OdeTab*)(base + L.ode);
     b.Epart = L.Epart >= 0 ? (cd*)(base + L.Epart) : nullptr;
     c->d_ode = (OdeInst*)(base + L.odeinst);
+    c->E0 = L.E0 >= 0 ? (cd*)(base + L.E0) : nullptr;
+    c->Mu = L.Mu >= 0 ? (cd*)(base + L.Mu) : nullptr;
+    c->mupart = L.mupart >= 0 ? (cd*)(base + L.mupart) : nullptr;
+    c->mu_row = -1;
     c->row = -1;
     c->strip_row = -1;
     c->boundary_ready = 0;
@@ -295,6 +306,7 @@ int ctx_boundary_status(fdtd_ctx* c, int st)
     if (st & STATUS_NONFINITE) return fail(c, FDTD_ERANGE, "non-finite boundary value");
     c->row = 0;
     c->strip_row = 0;
+    c->mu_row = c->mupart ? 0 : -1;
     c->boundary_ready = 1;
     return FDTD_OK;
 }
@@ -339,6 +351,7 @@ int fdtd_set_boundary(fdtd_ctx* c)
     if (rc) return rc;
     c->row = 0;
     c->strip_row = 0;
+    c->mu_row = c->mupart ? 0 : -1;
     c->boundary_ready = 1;
     return FDTD_OK;
 }
@@ -355,6 +368,7 @@ int fdtd_set_boundary_tables(fdtd_ctx* c, const double* h_E, int64_t n)
     if (rc) return rc;
     c->row = 0;
     c->strip_row = 0;
+    c->mu_row = c->mupart ? 0 : -1;
     c->boundary_ready = 1;
     return FDTD_OK;
 }
@@ -381,6 +395,12 @@ static int march_to(fdtd_ctx* c, int64_t target)
         }
         int rc = launch_block(c, m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
         if (rc) return rc;
+        if (c->mupart) {
+            // rows m0..m1 are complete and still in the ring
+            rc = launch_mu_rows(c, m0, m1);
+            if (rc) return rc;
+            c->mu_row = m1;
+        }
         c->row = m1;
         if (s1 >= s0) c->strip_row = s1;
     }
@@ -438,6 +458,23 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.chi;
         break;
+    case FDTD_RO_MU:
+        if (!c->mupart) return fail(c, FDTD_EINVAL, "mu is defined for stimulated emission (FDTD_INC_EXP1) only");
+        if (count > c->mu_row + 1)
+            return fail(c, FDTD_ESTATE, "mu holds %lld rows (fdtd_march accumulates it, batches do not)",
+                        (long long)(c->mu_row + 1));
+        rc = launch_mu_final(c, count, dst_on_device ? (cd*)dst : c->Mu);
+        if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
+        src = c->Mu;
+        break;
+    case FDTD_RO_LAMBDA:
+        esz = 8;
+        if (!c->E0) return fail(c, FDTD_EINVAL, "lambda is defined for stimulated emission (FDTD_INC_EXP1) only");
+        if (count > c->row + 1) return fail(c, FDTD_ESTATE, "only %lld rows marched", (long long)(c->row + 1));
+        rc = launch_lambda_final(c, count, dst_on_device ? (double*)dst : c->b.Pe);
+        if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
+        src = c->b.Pe;
+        break;
     case FDTD_RO_E:
         if (count > c->p.Nt + 1) return fail(c, FDTD_ESIZE, "E has Nt+1 values");
         if (dst_on_device) {
@@ -463,9 +500,10 @@ struct CkptHeader {
     char magic[8];
     uint32_t version, header_bytes;
     fdtd_params p;
-    int64_t row, strip_row, boundary_ready, ws_bytes;
+    int64_t row, strip_row, boundary_ready, ws_bytes, mu_row;
 };
 static const char CKPT_MAGIC[8] = {'F', 'D', 'T', 'D', 'C', 'K', 'P', '1'};
+static const uint32_t CKPT_VERSION = 2;
 
 int fdtd_checkpoint_size(const fdtd_ctx* c, size_t* bytes)
 {
@@ -483,13 +521,14 @@ int fdtd_checkpoint(fdtd_ctx* c, void* h_dst, size_t bytes)
     CkptHeader h;
     memset(&h, 0, sizeof h);
     memcpy(h.magic, CKPT_MAGIC, sizeof h.magic);
-    h.version = 1;
+    h.version = CKPT_VERSION;
     h.header_bytes = (uint32_t)sizeof h;
     h.p = c->p;
     h.row = c->row;
     h.strip_row = c->strip_row;
     h.boundary_ready = c->boundary_ready;
     h.ws_bytes = ws_bytes(c);
+    h.mu_row = c->mu_row;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync((char*)h_dst + sizeof h, c->b.ring, (size_t)ws_bytes(c), hipMemcpyDeviceToHost, c->stream);
@@ -505,7 +544,7 @@ int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
     if (!h_src || bytes < sizeof(CkptHeader)) return fail(c, FDTD_EINVAL, "not a checkpoint");
     CkptHeader h;
     memcpy(&h, h_src, sizeof h);
-    if (memcmp(h.magic, CKPT_MAGIC, sizeof h.magic) || h.version != 1 || h.header_bytes != sizeof h)
+    if (memcmp(h.magic, CKPT_MAGIC, sizeof h.magic) || h.version != CKPT_VERSION || h.header_bytes != sizeof h)
         return fail(c, FDTD_EINVAL, "not a checkpoint of this library");
     if (memcmp(&h.p, &c->p, sizeof h.p) || h.ws_bytes != ws_bytes(c))
         return fail(c, FDTD_EINVAL, "checkpoint of other parameters");
@@ -524,6 +563,7 @@ int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
     c->row = h.row;
     c->strip_row = h.strip_row;
     c->boundary_ready = (int)h.boundary_ready;
+    c->mu_row = h.mu_row;
     return FDTD_OK;
 }
 

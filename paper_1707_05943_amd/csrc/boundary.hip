@@ -291,6 +291,25 @@ __global__ __launch_bounds__(64) void k_E_ode(const OdeInst* __restrict__ tab)
     }
 }
 
+// e0(t_r) of App. D: the emitter amplitude of the one-excitation problem
+// with the exponential packet of Eq. (7) and the emitter in its ground state
+// at t = 0, i.e. the delay series of the exponential packet (A = i sqrt(alpha
+// G), lambda = ik + alpha G/2) without the two-photon prefactor
+__global__ __launch_bounds__(64) void k_E0(Geom g, Packet pk, cd* __restrict__ E0, int* status)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > g.Nt) return;
+    int range_flag = 0;
+    const cd lam = mk(0.5 * pk.alpha * pk.Gamma, pk.k);
+    const cd A = mk(0.0, sqrt(pk.alpha * pk.Gamma));
+    double s, c;
+    sincos(-pk.k * g.a, &s, &c);
+    const cd e = A * mk(c, s) * delay_series(g, lam, r, &range_flag);
+    E0[r] = e;
+    if (range_flag) atomicOr(status, STATUS_GAMMA_RANGE);
+    if (!isfinite(e.re) || !isfinite(e.im)) atomicOr(status, STATUS_NONFINITE);
+}
+
 __global__ void k_clear_status(int* st)
 {
     if (threadIdx.x == 0) *st = 0;
@@ -370,6 +389,20 @@ int launch_boundary_post(fdtd_ctx* c)
     // row 0 of the ring is the initial condition (zero for x > -a)
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->b.ring, c->g.C);
     hipLaunchKernelGGL(k_md_row0, dim3((unsigned)((c->g.D + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b);
+    if (hipGetLastError() != hipSuccess) return FDTD_EDEVICE;
+    // stimulated emission: e0 and row 0 of mu
+    if (c->E0) {
+        int rc = launch_e0(c);
+        if (!rc) rc = launch_mu_rows(c, 0, 0);
+        if (rc) return rc;
+    }
+    return FDTD_OK;
+}
+
+int launch_e0(fdtd_ctx* c)
+{
+    hipLaunchKernelGGL(k_E0, dim3((unsigned)((c->g.Nt + 64) / 64)), dim3(64), 0, c->stream, c->g, c->pk, c->E0,
+                       c->b.status);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 

@@ -147,6 +147,13 @@ struct fdtd_ctx {
     int64_t strip_row;    // last strip row marched (>= row)
     int boundary_ready;
     int64_t nblk;         // per-row partial sums of |psi|^2 (one per workgroup)
+    // stimulated emission only (NULL / -1 otherwise): the one-excitation
+    // emitter amplitude e0(t_r), per-row partial sums of mu(t_r), and the
+    // last row whose partial sums are complete
+    cd* E0;
+    cd* Mu;               // mu(t_r) readout staging (Nt+1)
+    cd* mupart;           // (Nt+1) x NM_BLOCKS
+    int64_t mu_row;
     char err[512];
 };
 
@@ -164,6 +171,14 @@ int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst);
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst);
 int launch_clear(fdtd_ctx* c);
+// non-Markovian measures of stimulated emission: e0(t_r) into c->E0; the
+// partial sums of mu over rows r0..r1 (complete rows of the ring); the
+// readouts mu(t_r) and lambda(t_r) for r < nrows
+constexpr int NM_BLOCKS = 64;
+int launch_e0(fdtd_ctx* c);
+int launch_mu_rows(fdtd_ctx* c, int64_t r0, int64_t r1);
+int launch_mu_final(fdtd_ctx* c, int64_t nrows, cd* dst);
+int launch_lambda_final(fdtd_ctx* c, int64_t nrows, double* dst);
 
 constexpr int MAX_HALO = 64;
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 FDTD_ABI_VERSION = 1
 INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
-RO_ROW, RO_PE, RO_CHI, RO_E = 1, 2, 3, 4
+RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA = 1, 2, 3, 4, 5, 6
 E_SERIES, E_DELAY_ODE = 0, 1
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", -4: "FDTD_EDEVICE",
           -5: "FDTD_ERANGE"}
@@ -207,6 +207,14 @@ class Solver:
 
     def chi(self, count: int) -> np.ndarray:
         return self._ro(RO_CHI, 0, count, np.complex128)
+
+    def mu(self, count: int | None = None) -> np.ndarray:
+        """mu(t_r) of App. D (stimulated-emission instances)"""
+        return self._ro(RO_MU, 0, self.row + 1 if count is None else count, np.complex128)
+
+    def lam(self, count: int | None = None) -> np.ndarray:
+        """lambda(t_r) of App. D (stimulated-emission instances)"""
+        return self._ro(RO_LAMBDA, 0, self.row + 1 if count is None else count, np.float64)
 
     def E(self) -> np.ndarray:
         """the boundary table c E(t_r)"""

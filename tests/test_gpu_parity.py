@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle import nm
 from paper_1707_05943_amd import fdtd
 from paper_1707_05943_amd import workloads as W
 
@@ -311,6 +312,49 @@ def test_checkpoint_restore_is_bitwise(name):
     with pytest.raises(fdtd.FdtdError) as e:
         c.restore(ck[: ck.size // 2])
     assert e.value.code == -2
+
+
+NM_CASES = {
+    "exp1": MARCH_CASES["exp1"],
+    # strip wider than a block of rows, several strip workgroups, Nt > Nx
+    "exp1_D1200": W.Instance(name="exp1_D1200", Nx=3100, D=1200, Nt=3400, Delta=0.0025, omega0=2.0, Gamma=1.5,
+                             incident=W.INC_EXP1, k=2.3, alpha=0.5),
+}
+
+
+@pytest.mark.parametrize("name", list(NM_CASES))
+def test_nonmarkovian_measures(name):
+    """mu(t_r) and lambda(t_r) of App. D for every row, accumulated across
+    resumed marches, against the oracle; a checkpoint carries them."""
+    inst = NM_CASES[name]
+    _say(f"[parity] non-Markovian measures: {name}")
+    ref = nm.measures(inst, range(inst.Nt + 1))
+    sol = fdtd.Solver(inst).set_boundary()
+    sol.march(117)
+    ck = sol.checkpoint()
+    sol.march(inst.Nt - 117)
+    mu, lam = sol.mu(), sol.lam()
+    assert mu.shape == (inst.Nt + 1,) and lam.shape == (inst.Nt + 1,)
+    assert rel_l2(mu, ref["mu"]) <= TOL, rel_l2(mu, ref["mu"])
+    assert rel_l2(lam, ref["lambda"]) <= TOL, rel_l2(lam, ref["lambda"])
+    # a restored march accumulates the same mu bit for bit
+    again = fdtd.Solver(inst).set_boundary().restore(ck)
+    assert np.array_equal(again.mu(), mu[:118])
+    again.march(inst.Nt - 117)
+    assert np.array_equal(again.mu(), mu)
+    assert np.array_equal(again.lam(), lam)
+    # no rows beyond the march
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.Solver(inst).set_boundary().march(5).mu(7)
+    assert e.value.code == -3
+
+
+def test_nonmarkovian_measures_need_stimulated_emission():
+    sol = fdtd.Solver(MARCH_CASES["exp2"]).set_boundary().march(3)
+    for f in (sol.mu, sol.lam):
+        with pytest.raises(fdtd.FdtdError) as e:
+            f()
+        assert e.value.code == -1
 
 
 def test_state_errors():
