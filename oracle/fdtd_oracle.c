@@ -225,8 +225,32 @@ static cplx E_exp1_closed(const orc_params *p, double t)
     return cexp(-W * t) * s;
 }
 
+/* Eq. (13) where its p = k - w0 + i (G/2)(1 - alpha) vanishes (k = w0 and
+ * alpha = 1: the packet decays at the emitter's rate, lambda = W), a removable
+ * 0/0 of the closed form.  Then phi(-a-s) = A e^{-ika} e^{-W s},
+ * A = i sqrt(alpha G), and the integrals of the delay series are elementary:
+ * J_n(T) = int_0^T (T-s)^n/n! e^{-W(T-s)} A e^{-ika} e^{-W s} ds
+ *        = A e^{-ika} e^{-W T} T^{n+1}/(n+1)!, so
+ * E(t) = sqrt(G/2) sum_n (G/2)^n [J_n(t - 2na) - J_n(t - 2(n+1)a)]. */
+static cplx E_exp2_resonant(const orc_params *p, double t)
+{
+    double a = half_a(p), G = p->Gamma;
+    cplx W = I * p->omega0 + G / 2.0;
+    cplx A = I * sqrt(p->alpha * G) * cexp(-I * p->k * a);
+    cplx s = 0.0;
+    for (int n = 0; t - 2.0 * n * a > 0.0; ++n) {
+        double T1 = t - 2.0 * n * a, T2 = t - 2.0 * (n + 1) * a;
+        cplx j = cexp((n + 1) * log(T1) - W * T1 - lgamma(n + 2.0));
+        if (T2 > 0.0) j -= cexp((n + 1) * log(T2) - W * T2 - lgamma(n + 2.0));
+        s += pow(G / 2.0, n) * j;
+    }
+    return sqrt(G / 2.0) * A * s;
+}
+
 /* closed form Eq. (13), multiplied by e^{-ika} so that phi's phase is the
- * one of Eq. (7) (the two must use the same packet). */
+ * one of Eq. (7) (the two must use the same packet).  Near p = 0 its two
+ * terms cancel (relative rounding ~ 1e-16/|p|); at p = 0 exactly the limit
+ * above is taken. */
 static cplx E_exp2_closed(const orc_params *p, double t)
 {
     double a = half_a(p), G = p->Gamma, k = p->k, w0 = p->omega0, al = p->alpha;
@@ -234,6 +258,7 @@ static cplx E_exp2_closed(const orc_params *p, double t)
     cplx lam = I * k + al * G / 2.0;
     cplx pp = k - w0 + I * G / 2.0 * (1.0 - al);
     if (t <= 0.0) return 0.0;
+    if (creal(pp) == 0.0 && cimag(pp) == 0.0) return E_exp2_resonant(p, t);
     cplx e = sqrt(al * G * G / 2.0) * (cexp(-W * t) - cexp(-lam * t)) / pp;
     for (int n = 1; t - 2.0 * n * a > 0.0; ++n) {
         double T = t - 2.0 * n * a;

@@ -35,16 +35,30 @@ PLANE_RES = _inst(W.INC_PLANE, k=3.0)
 EXP_A = _inst(W.INC_EXP2, alpha=0.7)
 EXP_B = _inst(W.INC_EXP2, alpha=1.6, k=3.0)          # p on the negative imaginary axis: Re z < 0
 EXP_C = _inst(W.INC_EXP2, alpha=2.5, k=2.2, D=30)
+EXP_RES = _inst(W.INC_EXP2, alpha=1.0, k=3.0)         # p = 0: Eq. (13)'s removable 0/0
 GAUSS = W.tiny_gauss(D=20, Nx=10, Nt=100, Delta=0.05, width=0.6)
 GAUSS.x0 = -GAUSS.a - 8 * GAUSS.width
 
 
-@pytest.mark.parametrize("inst", [PLANE, PLANE_RES, EXP_A, EXP_B, EXP_C], ids=["plane", "plane_res", "expA", "expB", "expC"])
+@pytest.mark.parametrize("inst", [PLANE, PLANE_RES, EXP_A, EXP_B, EXP_C, EXP_RES],
+                         ids=["plane", "plane_res", "expA", "expB", "expC", "exp_p0"])
 def test_closed_form_matches_quadrature(inst):
     t = np.array([0.03, 0.4, 0.99, 1.0, 1.01, 2.5, 3.7, 5.0, 7.3])
     c = oracle.E_closed(inst, t)
     q = oracle.E_quad(inst, t)
     assert np.max(np.abs(c - q)) < 1e-12 * max(1.0, np.max(np.abs(q)))
+
+
+def test_eq13_is_continuous_at_p0():
+    """alpha = 1 -+ 1e-7 on resonance: the closed form (its terms cancel to
+    ~1e-16/|p| ~ 4e-9) lies within the O(|p| t) change of E of the p = 0 limit."""
+    import dataclasses
+    t = np.array([0.4, 1.0, 2.5, 5.0])
+    e0 = oracle.E_closed(EXP_RES, t)
+    for al in (1.0 - 1e-7, 1.0 + 1e-7):
+        e = oracle.E_closed(dataclasses.replace(EXP_RES, alpha=al), t)
+        assert np.max(np.abs(e - e0)) <= 2e-6 * np.max(np.abs(e0))
+        assert np.max(np.abs(e - e0)) > 0.0
 
 
 def test_eq13_needs_the_phase_factor():
