@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["large", "small", "batch"], default="large")
+    ap.add_argument("--workload", choices=["large", "small", "batch", "nm"], default="large")
     ap.add_argument("--batch", type=int, default=512, help="instances of the batched sweep")
     ap.add_argument("--batch-seed", type=int, default=7)
     ap.add_argument("--no-batch", action="store_true", help="leave the batched sweep out of the default line")
@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--sweep-train", type=int, default=2048, help="training instances of the surrogate")
     ap.add_argument("--sweep-steps", type=int, default=3000, help="Adam steps of the surrogate")
     ap.add_argument("--sweep-points", type=int, default=1024, help="points of the surrogate sweep")
+    ap.add_argument("--no-nm", action="store_true",
+                    help="leave the stimulated-emission march with the measures of App. D out of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=600, help="rows past D in the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -182,6 +184,76 @@ def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
             "ring_GB": sum((i.D + 2 * best.tmax + 2) * (i.Nx + 1) * 16 for i in insts) / 1e9}
 
 
+def run_nm(steps: int, warmup: int, base_march_ms: float | None = None) -> dict:
+    """The stimulated-emission instance on the large grid, marched with the
+    non-Markovian measures of App. D: mu's row sums follow every march launch
+    (k_mu_rows); mu(t_r) and lambda(t_r) for every row and N_geo are read into
+    device memory after the march.  k_block does the same work as for the Gaussian
+    on this grid (same plan), so the march time minus the Gaussian's is the
+    cost of k_mu_rows: 16 B per cell of row r inside the photon field's
+    support, columns j <= min(Nx, r + D), read once more from HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1707_05943_amd import fdtd
+    from paper_1707_05943_amd import workloads as W
+
+    inst = W.large_stimulated()
+    dev = torch.device("cuda:0")
+    sol = fdtd.Solver(inst, device=str(dev))
+    stream = torch.cuda.current_stream(dev)
+    mu_dev = torch.empty(2 * (inst.Nt + 1), dtype=torch.float64, device=dev)
+    lam_dev = torch.empty(inst.Nt + 1, dtype=torch.float64, device=dev)
+    ngeo_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    lib = sol.lib
+
+    def step(ev=None):
+        sol._check(lib.fdtd_set_boundary(sol.ctx))
+        if ev is not None:
+            ev[0].record(stream)
+        sol._check(lib.fdtd_march(sol.ctx, inst.Nt))
+        if ev is not None:
+            ev[1].record(stream)
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_MU, 0, ctypes.c_void_p(mu_dev.data_ptr()), inst.Nt + 1, 1))
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_LAMBDA, 0, ctypes.c_void_p(lam_dev.data_ptr()),
+                                    inst.Nt + 1, 1))
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_NGEO, inst.Nt, ctypes.c_void_p(ngeo_dev.data_ptr()), 1, 1))
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    march_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    mu = mu_dev.view(-1, 2).cpu().numpy()
+    lam = lam_dev.cpu().numpy()
+    T = fdtd.describe(inst)["T"]
+    launches = (inst.Nt + T - 1) // T
+    r = np.arange(1, inst.Nt + 1, dtype=np.float64)
+    mu_bytes = 16.0 * float(np.sum(np.minimum(inst.Nx + 1, r + inst.D + 1)))
+    out = {"workload": inst.name, "ms_per_step": ms_step, "march_ms": march_ms,
+           "cell_updates_per_s": inst.Nx * inst.Nt / (ms_step * 1e-3),
+           "mu_end": [float(mu[-1, 0]), float(mu[-1, 1])], "lambda_end": float(lam[-1]),
+           "n_geo": float(ngeo_dev.cpu()[0]),
+           "k_mu_rows_launches": launches, "k_mu_rows_bytes_per_launch": mu_bytes / launches}
+    if base_march_ms is not None and march_ms > base_march_ms:
+        mu_ms = march_ms - base_march_ms
+        out["mu_ms"] = mu_ms
+        out["k_mu_rows_avg_us"] = mu_ms * 1e3 / launches
+        gbs = mu_bytes / (mu_ms * 1e-3) / 1e9
+        out["k_mu_rows_achieved_GBps"] = gbs
+        out["k_mu_rows_hbm_frac"] = gbs / HBM_PEAK_GBS
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_sweep(n_train: int, n_pts: int, steps: int, tol: float = 1e-3) -> dict:
     """Surrogate training and the surrogate-with-fallback sweep against the
     plain batched solver, on points drawn from the batched sweep's
@@ -291,6 +363,15 @@ def main():
     from paper_1707_05943_amd import fdtd
     from paper_1707_05943_amd import workloads as W
 
+    if args.workload == "nm":
+        nm = run_nm(args.steps, args.warmup)
+        print(json.dumps({"metric": METRIC, "value": nm["cell_updates_per_s"], "unit": "cell-updates/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": nm["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": nm["workload"]}, "nm": nm}), flush=True)
+        return
+
     if args.workload == "batch":
         b = run_batch(args.batch, args.batch_seed, args.steps, args.warmup)
         print(json.dumps({"metric": METRIC, "value": b["cell_updates_per_s"], "unit": "cell-updates/s",
@@ -368,6 +449,12 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows)
+    if args.workload == "large" and not args.no_nm:
+        print("[bench] stimulated emission with the measures of App. D", file=sys.stderr, flush=True)
+        try:
+            out["nm"] = run_nm(args.steps, args.warmup, march_ms)
+        except Exception as e:
+            out["nm"] = {"error": f"{type(e).__name__}: {e}"}
     if args.workload == "large" and not args.no_batch:
         print(f"[bench] batched sweep of {args.batch} instances", file=sys.stderr, flush=True)
         try:

@@ -145,8 +145,11 @@ enum fdtd_readout_kind {
     FDTD_RO_MU = 5,    /* mu(t_r) = int phi*(x,t_r) psi(x,t_r) dx for r = 0..count-1, complex; accumulated row
                           by row by fdtd_march (count <= current+1; instances of a batch hold row 0 only,
                           FDTD_ESTATE beyond) */
-    FDTD_RO_LAMBDA = 6 /* lambda(t_r) = int |psi(x,t_r)|^2 dx - |e0(t_r)|^2 for r = 0..count-1 (count <= current+1),
+    FDTD_RO_LAMBDA = 6,/* lambda(t_r) = int |psi(x,t_r)|^2 dx - |e0(t_r)|^2 for r = 0..count-1 (count <= current+1),
                           doubles; the determinant of the dynamical map is |mu|^2 lambda */
+    FDTD_RO_NGEO = 7   /* the geometric measure N_geo (App. D) over [0, t_arg], 0 <= arg <= current (as mu):
+                          the integral of d|det M_t|/dt where it is positive, |det M_t| = |mu|^2 |lambda|
+                          taken linear between rows (the sum of its positive increments); count = 1 double */
 };
 
 /* Copy a readout into dst: a device pointer (dst_on_device = 1, enqueued on

@@ -69,6 +69,16 @@ def one_excitation_norm(inst, e0: np.ndarray, r: int) -> float:
     return float(below + _trapezoid(np.abs(ph) ** 2, inst.Delta) + abs(e0[r]) ** 2)
 
 
+def n_geo(mu: np.ndarray, lam: np.ndarray) -> float:
+    """The geometric measure of App. D, N_geo = integral of d|det M_t|/dt over
+    the times where it is positive, det M_t = |mu(t)|^2 lambda(t), for samples
+    on consecutive rows: |det M| is taken linear between rows, so the
+    integral is the sum of its positive increments."""
+    d = np.abs(np.abs(np.asarray(mu)) ** 2 * np.asarray(lam))
+    inc = np.diff(d)
+    return float(np.sum(inc[inc > 0.0]))
+
+
 def measures(inst, rows, E1: np.ndarray | None = None) -> dict:
     """mu(t_r) and lambda(t_r) at the given rows from the oracle's march"""
     assert inst.incident == W.INC_EXP1

@@ -396,8 +396,10 @@ static int march_to(fdtd_ctx* c, int64_t target)
         int rc = launch_block(c, m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
         if (rc) return rc;
         if (c->mupart) {
-            // rows m0..m1 are complete and still in the ring
-            rc = launch_mu_rows(c, m0, m1);
+            // rows m0..m1 are complete and still in the ring.  (On a second
+            // stream these sums would take CUs the next march launch needs
+            // whole, and delay it more than they save.)
+            rc = launch_mu_rows(c, m0, m1, c->stream);
             if (rc) return rc;
             c->mu_row = m1;
         }
@@ -474,6 +476,16 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         rc = launch_lambda_final(c, count, dst_on_device ? (double*)dst : c->b.Pe);
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.Pe;
+        break;
+    case FDTD_RO_NGEO:
+        esz = 8;
+        if (!c->mupart) return fail(c, FDTD_EINVAL, "N_geo is defined for stimulated emission (FDTD_INC_EXP1) only");
+        if (count != 1) return fail(c, FDTD_ESIZE, "N_geo is one value");
+        if (arg < 0 || arg > c->mu_row)
+            return fail(c, FDTD_ESTATE, "mu holds rows 0..%lld", (long long)c->mu_row);
+        rc = launch_ngeo(c, arg, dst_on_device ? (double*)dst : (double*)c->b.chi);
+        if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
+        src = c->b.chi;
         break;
     case FDTD_RO_E:
         if (count > c->p.Nt + 1) return fail(c, FDTD_ESIZE, "E has Nt+1 values");

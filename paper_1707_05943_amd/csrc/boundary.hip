@@ -393,7 +393,7 @@ int launch_boundary_post(fdtd_ctx* c)
     // stimulated emission: e0 and row 0 of mu
     if (c->E0) {
         int rc = launch_e0(c);
-        if (!rc) rc = launch_mu_rows(c, 0, 0);
+        if (!rc) rc = launch_mu_rows(c, 0, 0, c->stream);
         if (rc) return rc;
     }
     return FDTD_OK;

@@ -174,11 +174,12 @@ int launch_clear(fdtd_ctx* c);
 // non-Markovian measures of stimulated emission: e0(t_r) into c->E0; the
 // partial sums of mu over rows r0..r1 (complete rows of the ring); the
 // readouts mu(t_r) and lambda(t_r) for r < nrows
-constexpr int NM_BLOCKS = 64;
+constexpr int NM_BLOCKS = 256;
 int launch_e0(fdtd_ctx* c);
-int launch_mu_rows(fdtd_ctx* c, int64_t r0, int64_t r1);
+int launch_mu_rows(fdtd_ctx* c, int64_t r0, int64_t r1, hipStream_t s);
 int launch_mu_final(fdtd_ctx* c, int64_t nrows, cd* dst);
 int launch_lambda_final(fdtd_ctx* c, int64_t nrows, double* dst);
+int launch_ngeo(fdtd_ctx* c, int64_t R, double* dst);   // N_geo over rows 0..R (uses the Mu and Pe staging)
 
 constexpr int MAX_HALO = 64;
 

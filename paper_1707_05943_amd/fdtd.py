@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
 FDTD_ABI_VERSION = 1
 INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
-RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA = 1, 2, 3, 4, 5, 6
+RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA, RO_NGEO = 1, 2, 3, 4, 5, 6, 7
 E_SERIES, E_DELAY_ODE = 0, 1
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", -4: "FDTD_EDEVICE",
           -5: "FDTD_ERANGE"}
@@ -216,6 +216,10 @@ class Solver:
         """lambda(t_r) of App. D (stimulated-emission instances)"""
         return self._ro(RO_LAMBDA, 0, self.row + 1 if count is None else count, np.float64)
 
+    def n_geo(self, row: int | None = None) -> float:
+        """the geometric measure N_geo of App. D over [0, t_row] (default: the current row)"""
+        return float(self._ro(RO_NGEO, self.row if row is None else row, 1, np.float64)[0])
+
     def E(self) -> np.ndarray:
         """the boundary table c E(t_r)"""
         return self._ro(RO_E, 0, self.p.Nt + 1, np.complex128)
@@ -361,6 +365,13 @@ class Batch:
 
     def E(self, i: int) -> np.ndarray:
         return self._ro(i, RO_E, 0, self._p(i).Nt + 1, np.complex128)
+
+    def lam(self, i: int, count: int | None = None) -> np.ndarray:
+        """lambda(t_r) of App. D for a stimulated-emission instance (mu is not tracked in batches)"""
+        return self._ro(i, RO_LAMBDA, 0, self._p(i).Nt + 1 if count is None else count, np.float64)
+
+    def mu(self, i: int, count: int) -> np.ndarray:
+        return self._ro(i, RO_MU, 0, count, np.complex128)
 
     def sync(self):
         self._check(self.lib.fdtd_batch_sync(self.h))

@@ -85,6 +85,16 @@ def large_gauss(seed: int = 2) -> Instance:
                              k0a=0.5 * math.pi, width=1.0, Nx=262144, Nt=131072, seed=seed)
 
 
+def large_stimulated() -> Instance:
+    """Stimulated emission (Eqs. 7-9) on the grid of large_gauss (D=10000,
+    Nx=262144, Nt=131072, Delta=1e-3, Gamma=1, k0*a=pi/2 on resonance): an
+    exponential packet with alpha=0.5 meets the excited emitter.  The family
+    the non-Markovian measures of App. D are defined for."""
+    k0 = 0.5 * math.pi / 5.0
+    return Instance(name="stim_D10000_Nx262144_Nt131072", Nx=262144, D=10000, Nt=131072, Delta=1e-3, omega0=k0,
+                    Gamma=1.0, incident=INC_EXP1, k=k0, alpha=0.5)
+
+
 def paper_sets() -> dict:
     """The parameter sets of the paper's validation figures: a two-photon plane
     wave (identical photons, Eqs. 5-6) in the paper's absolute units, Ny = Nt + 1.

@@ -203,3 +203,30 @@ def test_chi_snapshots_and_pe_samples(oracle_runs):
             _say(f"[batch] chi snapshot {inst.name} row {rows[i]} stride {strides[i]}: {e:.2e}")
             assert e <= TOL, (rep, inst.name, "chi", e)
     bat.close()
+
+
+def test_batch_lambda_of_stimulated_emission():
+    """lambda(t_r) of App. D for stimulated-emission instances of a batch
+    (series and delay-equation boundaries) against the oracle; batches keep
+    mu of row 0 only."""
+    from oracle import nm
+    exp1 = dict(Nx=1500, D=24, Nt=400, Delta=0.02, omega0=2.0, Gamma=1.5, incident=W.INC_EXP1, k=2.3, alpha=0.5)
+    cases = [W.Instance(name="exp1_series", **exp1), _gauss(10, 2600, 300, 0.02, 0.5, 36),
+             W.Instance(name="exp1_ode", **dict(exp1, D=40, Nt=520))]
+    cases[2].boundary = 1
+    _say("[batch] lambda of stimulated emission")
+    bat = fdtd.Batch(cases).set_boundary().march()
+    for i in (0, 2):
+        inst = cases[i]
+        ref = nm.measures(inst, range(inst.Nt + 1))
+        lam = bat.lam(i)
+        e = np.linalg.norm(lam - ref["lambda"]) / np.linalg.norm(ref["lambda"])
+        assert e <= TOL, (inst.name, e)
+        assert abs(bat.mu(i, 1)[0] - ref["mu"][0]) <= TOL
+        with pytest.raises(fdtd.FdtdError) as err:
+            bat.mu(i, 2)
+        assert err.value.code == -3
+    with pytest.raises(fdtd.FdtdError) as err:
+        bat.lam(1)
+    assert err.value.code == -1
+    bat.close()

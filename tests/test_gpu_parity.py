@@ -316,6 +316,8 @@ def test_checkpoint_restore_is_bitwise(name):
 
 NM_CASES = {
     "exp1": MARCH_CASES["exp1"],
+    # k = omega0 and alpha = 1: e0's series at b = W - lambda = 0 (the closed form's removable 0/0)
+    "exp1_p0": _fam("exp1_p0", W.INC_EXP1, alpha=1.0, Gamma=1.5, k=2.0),
     # strip wider than a block of rows, several strip workgroups, Nt > Nx
     "exp1_D1200": W.Instance(name="exp1_D1200", Nx=3100, D=1200, Nt=3400, Delta=0.0025, omega0=2.0, Gamma=1.5,
                              incident=W.INC_EXP1, k=2.3, alpha=0.5),
@@ -337,6 +339,12 @@ def test_nonmarkovian_measures(name):
     assert mu.shape == (inst.Nt + 1,) and lam.shape == (inst.Nt + 1,)
     assert rel_l2(mu, ref["mu"]) <= TOL, rel_l2(mu, ref["mu"])
     assert rel_l2(lam, ref["lambda"]) <= TOL, rel_l2(lam, ref["lambda"])
+    # N_geo over the whole march and over its first half
+    d = np.abs(np.abs(ref["mu"]) ** 2 * ref["lambda"])
+    scale = max(1.0, float(np.sum(np.abs(np.diff(d)))))
+    for R in (inst.Nt, inst.Nt // 2):
+        got, want = sol.n_geo(R), nm.n_geo(ref["mu"][: R + 1], ref["lambda"][: R + 1])
+        assert abs(got - want) <= TOL * scale, (R, got, want)
     # a restored march accumulates the same mu bit for bit
     again = fdtd.Solver(inst).set_boundary().restore(ck)
     assert np.array_equal(again.mu(), mu[:118])
@@ -347,11 +355,39 @@ def test_nonmarkovian_measures(name):
     with pytest.raises(fdtd.FdtdError) as e:
         fdtd.Solver(inst).set_boundary().march(5).mu(7)
     assert e.value.code == -3
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.Solver(inst).set_boundary().march(5).n_geo(6)
+    assert e.value.code == -3
+
+
+def test_nonmarkovian_measures_large_window():
+    """The stimulated-emission instance on the large grid (D=10000,
+    Nx=262144), marched on the GPU for D+600 rows in the launch configuration
+    the benchmark times.  Up to row r the field psi is zero right of column
+    r + D (the emitter radiates at -a and its mirror image at +a from t = 0,
+    at speed 1; the within-row recurrence underflows beyond a few columns),
+    and column j depends on columns <= j only, so the oracle on the first
+    2D+700 columns gives mu and lambda exactly."""
+    big = W.large_stimulated()
+    rows = big.D + 600
+    gpu_inst = W.with_sizes(big, Nt=rows)
+    win = W.with_sizes(big, Nx=rows + big.D + 100, Nt=rows)
+    sample = sorted(set(list(range(0, rows + 1, 97)) + [1, big.D - 1, big.D, big.D + 1, rows]))
+    _say(f"[parity] non-Markovian measures on {big.name}: rows={rows} window={win.Nx}")
+    ref = nm.measures(win, sample)
+    sol = fdtd.Solver(gpu_inst).set_boundary()
+    sol.march(rows)
+    mu, lam = sol.mu(), sol.lam()
+    assert rel_l2(mu[sample], ref["mu"]) <= TOL, rel_l2(mu[sample], ref["mu"])
+    assert rel_l2(lam[sample], ref["lambda"]) <= TOL, rel_l2(lam[sample], ref["lambda"])
+    # t = 0: e1(0) = 1 and the trapezoid's endpoint term Delta/2 |phi_in(-a)|^2
+    assert abs(mu[0] - (1.0 + 0.5 * big.Delta * big.alpha * big.Gamma)) <= 1e-15
+    sol.close()
 
 
 def test_nonmarkovian_measures_need_stimulated_emission():
     sol = fdtd.Solver(MARCH_CASES["exp2"]).set_boundary().march(3)
-    for f in (sol.mu, sol.lam):
+    for f in (sol.mu, sol.lam, sol.n_geo):
         with pytest.raises(fdtd.FdtdError) as e:
             f()
         assert e.value.code == -1

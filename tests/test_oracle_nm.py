@@ -55,3 +55,26 @@ def test_uncoupled_limit(dl, bound):
     for mu, r in zip(m["mu"], m["rows"]):
         assert abs(mu * np.exp(1j * inst.omega0 * r * inst.Delta) - 1.0) <= bound
     assert np.all(np.abs(m["lambda"] - 1.0) <= bound)
+
+
+def test_n_geo_of_closed_forms():
+    """N_geo is the integral of the positive part of d|det|/dt: zero for a
+    decaying |det|, the total rise for |det| = |cos t| on [0, 2 pi] (two rises
+    of 1), and for det = e^{-t} (1 + 0.5 sin 3t) the sum of the rises of the
+    continuous function between its critical points, to the sampling error."""
+    t = np.linspace(0.0, 2.0 * np.pi, 20001)
+    assert nm.n_geo(np.exp(-0.25 * t), np.ones_like(t)) == 0.0
+    assert abs(nm.n_geo(np.ones_like(t), np.cos(t)) - 2.0) <= 1e-12
+    # |mu|^2 lambda with mu = e^{-t/2} e^{i t}, lambda = 1 + 0.5 sin 3t
+    f = lambda x: np.exp(-x) * (1.0 + 0.5 * np.sin(3.0 * x))
+    mu = np.exp(-0.5 * t + 1j * t)
+    got = nm.n_geo(mu, 1.0 + 0.5 * np.sin(3.0 * t))
+    # critical points: f' = e^{-x} (1.5 cos 3x - 1 - 0.5 sin 3x) = 0
+    from scipy.optimize import brentq
+    g = lambda x: 1.5 * np.cos(3.0 * x) - 1.0 - 0.5 * np.sin(3.0 * x)
+    xs = np.linspace(0.0, 2.0 * np.pi, 4001)
+    crit = [brentq(g, a, b) for a, b in zip(xs[:-1], xs[1:]) if g(a) * g(b) < 0]
+    pts = np.concatenate(([0.0], crit, [2.0 * np.pi]))
+    ref = sum(max(0.0, f(b) - f(a)) for a, b in zip(pts[:-1], pts[1:]))
+    assert ref > 0.05
+    assert abs(got - ref) <= 2e-7       # extrema missed by the samples: O(h^2 f'') each
