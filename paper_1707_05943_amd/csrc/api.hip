@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include "fdtd_common.h"
+#include "nm.h"
 
 static char g_err[512];
 

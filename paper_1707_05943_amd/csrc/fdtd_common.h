@@ -179,7 +179,6 @@ int launch_e0(fdtd_ctx* c);
 int launch_mu_rows(fdtd_ctx* c, int64_t r0, int64_t r1, hipStream_t s);
 int launch_mu_final(fdtd_ctx* c, int64_t nrows, cd* dst);
 int launch_lambda_final(fdtd_ctx* c, int64_t nrows, double* dst);
-int launch_ngeo(fdtd_ctx* c, int64_t R, double* dst);   // N_geo over rows 0..R (uses the Mu and Pe staging)
 
 constexpr int MAX_HALO = 64;
 

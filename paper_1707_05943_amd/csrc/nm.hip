@@ -29,6 +29,7 @@
 // NM_BLOCKS workgroups whose partial sums k_mu_final adds in a fixed order.
 
 #include "fdtd_common.h"
+#include "nm.h"
 
 namespace {
 
