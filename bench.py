@@ -232,19 +232,15 @@ def run_nm(steps: int, warmup: int, base_march_ms: float | None = None) -> dict:
     march_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
     mu = mu_dev.view(-1, 2).cpu().numpy()
     lam = lam_dev.cpu().numpy()
-    T = fdtd.describe(inst)["T"]
-    launches = (inst.Nt + T - 1) // T
     r = np.arange(1, inst.Nt + 1, dtype=np.float64)
     mu_bytes = 16.0 * float(np.sum(np.minimum(inst.Nx + 1, r + inst.D + 1)))
     out = {"workload": inst.name, "ms_per_step": ms_step, "march_ms": march_ms,
            "cell_updates_per_s": inst.Nx * inst.Nt / (ms_step * 1e-3),
            "mu_end": [float(mu[-1, 0]), float(mu[-1, 1])], "lambda_end": float(lam[-1]),
-           "n_geo": float(ngeo_dev.cpu()[0]),
-           "k_mu_rows_launches": launches, "k_mu_rows_bytes_per_launch": mu_bytes / launches}
+           "n_geo": float(ngeo_dev.cpu()[0]), "k_mu_rows_bytes_per_step": mu_bytes}
     if base_march_ms is not None and march_ms > base_march_ms:
         mu_ms = march_ms - base_march_ms
         out["mu_ms"] = mu_ms
-        out["k_mu_rows_avg_us"] = mu_ms * 1e3 / launches
         gbs = mu_bytes / (mu_ms * 1e-3) / 1e9
         out["k_mu_rows_achieved_GBps"] = gbs
         out["k_mu_rows_hbm_frac"] = gbs / HBM_PEAK_GBS

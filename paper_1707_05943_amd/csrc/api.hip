@@ -379,15 +379,39 @@ int fdtd_set_boundary_tables(fdtd_ctx* c, const double* h_E, int64_t n)
 // over the next block.  A march that stopped inside a block resumes from the
 // block's first row, so every row is computed from the same block start
 // whatever the call boundaries (the results are bitwise the same).
+// mu's row sums (stimulated emission) are taken of complete rows while the
+// ring still holds them.  Rows wait for several launches and go in one
+// launch of up to MU_ROWS rows: before a launch that would overwrite the
+// oldest waiting row (it writes rows up to w; the slot of row p comes back
+// at p + R), once MU_ROWS rows wait, and at the end of the call.  (On a
+// second stream beside the march these sums would take CUs the next march
+// launch needs whole, and delay it more than they save.)
+constexpr int64_t MU_ROWS = 256;
+
 static int march_to(fdtd_ctx* c, int64_t target)
 {
-    const int64_t T = c->plan.T, Nt = c->p.Nt;
+    const int64_t T = c->plan.T, Nt = c->p.Nt, R = c->g.R;
+    int64_t p0 = -1, p1 = -1;                 // rows waiting for their mu sums
+    auto flush = [&]() -> int {
+        if (p0 < 0) return FDTD_OK;
+        int rc = launch_mu_rows(c, p0, p1, c->stream);
+        if (rc) return rc;
+        c->mu_row = p1;
+        p0 = p1 = -1;
+        return FDTD_OK;
+    };
     while (c->row < target) {
         const int64_t m0 = 1 + T * (c->row / T);
         const int64_t m1 = (m0 + T - 1 < target) ? m0 + T - 1 : target;
         int64_t s0 = c->strip_row + 1, s1 = -1;
         if (s0 <= Nt && s0 <= m0 + T) s1 = (s0 + T - 1 < Nt) ? s0 + T - 1 : Nt;
-        if (c->strip_row < m1) {
+        const bool strip_only = c->strip_row < m1;
+        const int64_t w = strip_only ? s1 : (s1 > m1 ? s1 : m1);
+        if (p0 >= 0 && w - p0 >= R) {
+            int rc = flush();
+            if (rc) return rc;
+        }
+        if (strip_only) {
             // the strip must hold every row this block reads: march it alone first
             int rc = launch_block(c, 1, 0, s0, s1);
             if (rc) return rc;
@@ -397,17 +421,14 @@ static int march_to(fdtd_ctx* c, int64_t target)
         int rc = launch_block(c, m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
         if (rc) return rc;
         if (c->mupart) {
-            // rows m0..m1 are complete and still in the ring.  (On a second
-            // stream these sums would take CUs the next march launch needs
-            // whole, and delay it more than they save.)
-            rc = launch_mu_rows(c, m0, m1, c->stream);
-            if (rc) return rc;
-            c->mu_row = m1;
+            if (p0 < 0) p0 = m0;
+            p1 = m1;
+            if (p1 - p0 + 1 >= MU_ROWS && (rc = flush())) return rc;
         }
         c->row = m1;
         if (s1 >= s0) c->strip_row = s1;
     }
-    return FDTD_OK;
+    return flush();
 }
 
 int fdtd_march(fdtd_ctx* c, int64_t n_rows)

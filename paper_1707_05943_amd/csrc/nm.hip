@@ -34,6 +34,7 @@
 namespace {
 
 constexpr int NM_THREADS = 256;
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 // conj(phi(x_j, t_r)) from the table values at q = r - j (Phi, e0) and
 // q + D (e0), loaded beforehand with clamped indices
@@ -88,7 +89,9 @@ __global__ __launch_bounds__(NM_THREADS) void k_mu_rows(Geom g, Bufs b, const cd
             q = q < 0 ? 0 : q;
             int64_t q2 = r - j + D;
             q2 = q2 < 0 ? 0 : (q2 > Nt ? Nt : q2);
-            psi[u] = row[j];
+            // the row is streamed once: a non-temporal load keeps the tables in L2
+            const v2d pv = __builtin_nontemporal_load(reinterpret_cast<const v2d*>(row + j));
+            psi[u] = mk(pv.x, pv.y);
             ph[u] = Phi[q];
             e1[u] = E0[q];
             e2[u] = E0[q2];
