@@ -30,6 +30,26 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_readout_kinds_match_header():
+    """the binding's readout codes are the header's enum values"""
+    txt = open(os.path.join(ROOT, "include", "fdtd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    enum = dict((k, int(v)) for k, v in re.findall(r"\bFDTD_(RO_[A-Z]+)\s*=\s*(\d+)", txt))
+    assert enum == {k: getattr(fdtd, k) for k in enum}
+    assert set(enum) == {"RO_ROW", "RO_PE", "RO_CHI", "RO_E", "RO_MU", "RO_LAMBDA", "RO_NGEO"}
+
+
+def test_workspace_grows_by_the_measures_for_stimulated_emission():
+    """stimulated emission adds e0, mu and mu's per-row partial sums
+    ((Nt + 1) x 256 complex doubles) to the workspace"""
+    base = dict(name="x", Nx=1500, D=24, Nt=400, Delta=0.02, omega0=2.0, Gamma=1.5, k=2.3, alpha=0.5)
+    exp1 = fdtd.workspace_size(W.Instance(incident=W.INC_EXP1, **base))
+    exp2 = fdtd.workspace_size(W.Instance(incident=W.INC_EXP2, **base))
+    n = base["Nt"] + 1
+    al = lambda b: (b + 255) // 256 * 256
+    assert exp1 - exp2 == al(16 * n) * 2 + al(16 * n * 256)
+
+
 def test_surrogate_sizes_on_the_host():
     from paper_1707_05943_amd import surrogate
     n, ws = surrogate.sizes(surrogate.cfg())
