@@ -351,7 +351,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+              "designed (column blocks per GPU, halos over xGMI) but not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
