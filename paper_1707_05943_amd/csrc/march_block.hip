@@ -778,15 +778,22 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             // barrier instead (see below).
             cd m0 = mA[i], m1 = mB[i];
             if constexpr (WIN) {
-                // window row q - ra = tau - j, column D - j - W.lo (32-bit: j < NT K)
+                // window row q - ra = tau - j, column D - j - W.lo (32-bit: j < NT K).
+                // Column 1 is the first cell of lane 0 only (the segment starts
+                // at column 1); column D takes the exact value below.
                 const int jj = (int)j;
                 const int wr = tau - jj;
                 const bool inwin = cell && wr >= 0;
-                const bool late = (jj == 1);
                 const cd* wp = &W.w[0][0] + (inwin ? wr * BM_TMAX + (dwl - jj) : 0);
                 const cd w0 = wp[0], w1 = wp[1];
-                m0 = csel(inwin, csel(j < D && !late, w0, zero()), m0);
-                m1 = csel(inwin, csel(!late, w1, zero()), m1);
+                if (i == 0) {
+                    const bool late = (jj == 1);
+                    m0 = csel(inwin, csel(!late, w0, zero()), m0);
+                    m1 = csel(inwin, csel(!late, w1, zero()), m1);
+                } else {
+                    m0 = csel(inwin, w0, m0);
+                    m1 = csel(inwin, w1, m1);
+                }
             }
             if (j == D) m0 = pq * et;                 // psi(0, q)
             cmac(v, c4, (q >= 0) ? m0 + m1 : zero());
