@@ -37,8 +37,9 @@ namespace {
 
 // e^L gamma*(n, z): the scale factor enters the exponent, so that products
 // like T^m gamma*(m+1, bT) that are moderate while their factors are not stay
-// representable
-__device__ inline cd gamma_star_x(int n, cd z, cd L, int* range_flag)
+// representable.  lf_n = log n! and lf_n1 = log (n-1)! come from the caller,
+// which steps them along its sum.
+__device__ inline cd gamma_star_x(int n, cd z, cd L, double lf_n, double lf_n1, int* range_flag)
 {
     const double az = cabs_(z);
     if (az <= (double)n + 0.5) {
@@ -51,7 +52,7 @@ __device__ inline cd gamma_star_x(int n, cd z, cd L, int* range_flag)
             if (norm2(term) <= 1e-36 * norm2(sum)) break;
             if (k == 19999) *range_flag = 1;
         }
-        return cexp_(L - z - mk(lgamma((double)n + 1.0), 0.0)) * sum;
+        return cexp_(L - z - mk(lf_n, 0.0)) * sum;
     }
     // z^{-n} - e^{-z} z^{-1}/(n-1)! sum_{i=0}^{n-1} (n-1)!/(n-1-i)! z^{-i}
     const cd zi = cdiv(mk(1.0, 0.0), z);
@@ -61,7 +62,7 @@ __device__ inline cd gamma_star_x(int n, cd z, cd L, int* range_flag)
         s += t;
     }
     const cd lz = clog_(z);
-    return cexp_(L - (double)n * lz) - cexp_(L - z - lz - mk(lgamma((double)n), 0.0)) * s;
+    return cexp_(L - (double)n * lz) - cexp_(L - z - lz - mk(lf_n1, 0.0)) * s;
 }
 
 // sum over round trips for phi(-a-s) = e^{-lambda s} (the factor A e^{-ika}
@@ -73,18 +74,21 @@ __device__ cd delay_series(const Geom& g, cd lam, int64_t r, int* range_flag)
     const cd gmb = mk(hg, 0.0) - b;           // G/2 - b
     const double lhg = log(hg);
     cd sum = mk(0.0, 0.0);
+    double lf_m = 0.0, lf_m1 = 0.0;                // log m!, log (m+1)!
     for (int64_t m = 0; m * g.D < r; ++m) {
+        lf_m = lf_m1;
+        lf_m1 = lf_m + log((double)m + 1.0);
         const int64_t q = r - m * g.D;
         const double T = (double)q * g.Delta;
         const double lT = log(T);
         const cd z = b * T;
         const cd mlT = -(lam * T);
         if (m == 0) {
-            sum += gamma_star_x(1, z, mlT + mk(lT, 0.0), range_flag);          // e^{-lam T} T gamma*(1, z)
+            sum += gamma_star_x(1, z, mlT + mk(lT, 0.0), 0.0, 0.0, range_flag);   // e^{-lam T} T gamma*(1, z)
         } else {
             const double lp = (double)(m - 1) * lhg + (double)m * lT;         // log (G/2)^{m-1} T^m
-            sum += gmb * gamma_star_x((int)m + 1, z, mlT + mk(lp + lT, 0.0), range_flag);
-            sum -= cexp_(mk(lp - lgamma((double)m + 1.0), 0.0) - g.W * T);
+            sum += gmb * gamma_star_x((int)m + 1, z, mlT + mk(lp + lT, 0.0), lf_m1, lf_m, range_flag);
+            sum -= cexp_(mk(lp - lf_m, 0.0) - g.W * T);
         }
     }
     return sqrt(hg) * sum;
@@ -96,13 +100,15 @@ __device__ cd stimulated(const Geom& g, int64_t r)
     const double hg = 0.5 * g.Gamma;
     const cd w2a = cexp_(g.W * (2.0 * g.a));
     cd s = mk(0.0, 0.0);
+    double lf = 0.0;                                // log n!
     for (int64_t n = 0; n * g.D <= r; ++n) {
         const double T = (double)(r - n * g.D) * g.Delta;
         if (n == 0) { s += mk(1.0, 0.0); continue; }
+        lf += log((double)n);
         // [(G/2) e^{2aW} T]^n / n!
         const cd base = (hg * T) * w2a;
         const cd lb = clog_(base);
-        s += cexp_((double)n * lb - mk(lgamma((double)n + 1.0), 0.0));
+        s += cexp_((double)n * lb - mk(lf, 0.0));
     }
     return cexp_(-(g.W * ((double)r * g.Delta))) * s;
 }
