@@ -184,9 +184,38 @@ int fdtd_destroy(fdtd_ctx *ctx);
 int fdtd_describe(const fdtd_params *p, char *buf, size_t n);
 
 /* Static text for a status code; text of the last failure of ctx (or of the
- * last failed fdtd_init / fdtd_workspace_size when ctx is NULL). */
+ * last failed fdtd_init / fdtd_workspace_size / fdtd_solve_noalloc when ctx
+ * is NULL). */
 const char *fdtd_strerror(int status);
 const char *fdtd_last_error(const fdtd_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  It does what fdtd_init + fdtd_set_boundary + fdtd_march(n_rows)
+ * + the P_e and row readouts into device memory do, with the same kernels and
+ * the same results bit for bit, but its workspace is a device array inside
+ * the library of FDTD_NOALLOC_MAX_BYTES, one per GPU, held from the library's
+ * load until the process ends.  It calls no hipMalloc, hipFree or other
+ * allocating routine, and needs no context.
+ *   p       instance parameters (as fdtd_init); their workspace
+ *           (fdtd_workspace_size) must fit in FDTD_NOALLOC_MAX_BYTES, else
+ *           FDTD_ESIZE and nothing is enqueued
+ *   n_rows  rows to march, 0..Nt
+ *   d_pe    device array of n_rows+1 doubles: P_e(t_r), r = 0..n_rows (as
+ *           FDTD_RO_PE), or NULL
+ *   d_row   device array of Nx+1 complex doubles: row n_rows (as FDTD_RO_ROW),
+ *           or NULL
+ *   hip_stream  the stream everything is enqueued on (NULL: default stream)
+ * The call waits for the boundary kernels (to report a gamma-series range
+ * error, FDTD_ERANGE), then enqueues the march and the readouts and returns;
+ * the outputs are complete when the stream is.  Every call on one GPU shares
+ * that GPU's array and overwrites it: calls that overlap in time on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller.  Errors: as fdtd_init and fdtd_march; the text is in
+ * fdtd_last_error(NULL). */
+#define FDTD_NOALLOC_MAX_BYTES (64ull << 20)
+int fdtd_solve_noalloc(const fdtd_params *p, int64_t n_rows, double *d_pe, void *d_row, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batches: n independent instances (each with its own grid, emitter and

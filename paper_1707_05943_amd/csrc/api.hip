@@ -202,13 +202,14 @@ int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn)
     return layout(p, P).total;
 }
 
-int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes, hipStream_t stream,
-               fdtd_ctx** out, char* why, size_t nwhy)
+// Fill the context *c (caller's storage) for parameters p over the caller's
+// workspace, and enqueue the clearing of the ring and the copies of the
+// boundary's step weights (waits for them).  Allocates nothing.
+static int ctx_setup(fdtd_ctx* c, const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes,
+                     hipStream_t stream, char* why, size_t nwhy)
 {
     int rc = ctx_validate(p, kn, why, nwhy);
     if (rc) return rc;
-    if (!out) { snprintf(why, nwhy, "out is NULL"); return FDTD_EINVAL; }
-    *out = nullptr;
     Plan P;
     plan_for(p, kn, &P, why, nwhy);
     const int64_t nblk = P.nwg;
@@ -219,8 +220,7 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     }
     if (((uintptr_t)d_workspace) & 255) { snprintf(why, nwhy, "workspace must be 256-byte aligned"); return FDTD_EINVAL; }
 
-    fdtd_ctx* c = (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx));
-    if (!c) { snprintf(why, nwhy, "out of host memory"); return FDTD_EDEVICE; }
+    memset(c, 0, sizeof *c);
     c->p = *p;
     c->stream = stream;
     c->nblk = nblk;
@@ -269,7 +269,6 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     c->boundary_ready = 0;
     rc = launch_clear(c);
     if (rc) {
-        free(c);
         snprintf(why, nwhy, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError()));
         return rc;
     }
@@ -285,9 +284,25 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_ode, &oi, sizeof oi, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-        free(c);
         snprintf(why, nwhy, "copy of the boundary tables failed: %s", hipGetErrorString(e));
         return FDTD_EDEVICE;
+    }
+    return FDTD_OK;
+}
+
+int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes, hipStream_t stream,
+               fdtd_ctx** out, char* why, size_t nwhy)
+{
+    int rc = ctx_validate(p, kn, why, nwhy);
+    if (rc) return rc;
+    if (!out) { snprintf(why, nwhy, "out is NULL"); return FDTD_EINVAL; }
+    *out = nullptr;
+    fdtd_ctx* c = (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx));
+    if (!c) { snprintf(why, nwhy, "out of host memory"); return FDTD_EDEVICE; }
+    rc = ctx_setup(c, p, kn, d_workspace, bytes, stream, why, nwhy);
+    if (rc) {
+        free(c);
+        return rc;
     }
     *out = c;
     return FDTD_OK;
@@ -652,3 +667,72 @@ const char* fdtd_strerror(int s)
 const char* fdtd_last_error(const fdtd_ctx* c) { return c ? c->err : g_err; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The allocation-free solve.  Its workspace is this file-scope array: each
+// GPU the library runs on holds one copy (at its own address) from the
+// library's load until the process ends.  In host code the array's name is
+// not a device address: the address is taken once per device with
+// hipGetSymbolAddress and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FDTD_NOALLOC_MAX_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];   // device address of `scratch` per device ordinal
+
+static int scratch_address(void** ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, FDTD_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(nullptr, FDTD_EDEVICE, "device ordinal %d beyond the %d this entry point serves", dev,
+                    NOALLOC_MAX_DEVICES);
+    if (!g_scratch_ptr[dev]) {
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a)
+            return fail(nullptr, FDTD_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s",
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = a;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return FDTD_OK;
+}
+
+extern "C" int fdtd_solve_noalloc(const fdtd_params* p, int64_t n_rows, double* d_pe, void* d_row, void* hip_stream)
+{
+    char why[256];
+    int rc = validate(p, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    if (n_rows < 0 || n_rows > p->Nt)
+        return fail(nullptr, FDTD_EINVAL, "n_rows = %lld outside 0..Nt = %lld", (long long)n_rows, (long long)p->Nt);
+    const int64_t need = ctx_bytes(p, SOLO_KNOBS);
+    if (need < 0 || need > (int64_t)FDTD_NOALLOC_MAX_BYTES)
+        return fail(nullptr, FDTD_ESIZE, "these parameters need %lld bytes of workspace, more than the %lld the "
+                    "allocation-free entry point holds (use fdtd_init with a workspace of your own)",
+                    (long long)need, (long long)FDTD_NOALLOC_MAX_BYTES);
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    // the context lives on this stack frame; its work is enqueued on the
+    // caller's stream and needs no host state after the return
+    fdtd_ctx c;
+    rc = ctx_setup(&c, p, SOLO_KNOBS, ws, (size_t)FDTD_NOALLOC_MAX_BYTES, (hipStream_t)hip_stream, why, sizeof why);
+    if (rc) return fail(nullptr, rc, "%s", why);
+    rc = launch_boundary(&c, 0);
+    if (rc) return fail(nullptr, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
+    rc = check_status(&c);
+    if (rc) return fail(nullptr, rc, "%s", c.err);
+    c.row = 0;
+    c.strip_row = 0;
+    c.mu_row = c.mupart ? 0 : -1;
+    c.boundary_ready = 1;
+    if (n_rows > 0 && (rc = march_to(&c, n_rows)))
+        return fail(nullptr, rc, "march launch failed: %s", hipGetErrorString(hipGetLastError()));
+    if (d_pe && (rc = launch_pe_final(&c, n_rows + 1, d_pe)))
+        return fail(nullptr, rc, "P_e readout launch failed");
+    if (d_row && (rc = launch_row_readout(&c, n_rows, (cd*)d_row)))
+        return fail(nullptr, rc, "row readout launch failed");
+    return FDTD_OK;
+}

@@ -29,7 +29,11 @@ EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_bo
            "fdtd_describe", "fdtd_strerror", "fdtd_last_error",
            "fdtd_batch_workspace_size", "fdtd_batch_init", "fdtd_batch_set_boundary", "fdtd_batch_march",
            "fdtd_batch_readout", "fdtd_batch_info", "fdtd_batch_sync", "fdtd_batch_destroy",
-           "fdtd_batch_last_error", "fdtd_batch_autotune", "fdtd_batch_set_chi", "fdtd_batch_sample_pe")
+           "fdtd_batch_last_error", "fdtd_batch_autotune", "fdtd_batch_set_chi", "fdtd_batch_sample_pe",
+           "fdtd_solve_noalloc")
+
+# bytes of the library's own workspace for fdtd_solve_noalloc (FDTD_NOALLOC_MAX_BYTES)
+NOALLOC_MAX_BYTES = 64 << 20
 
 
 class FdtdParams(ctypes.Structure):
@@ -101,6 +105,7 @@ def load(path: str = LIB_PATH):
     lib.fdtd_batch_autotune.argtypes = [P, i32, vp, ctypes.c_size_t, vp, i64, BO, ctypes.POINTER(ctypes.c_double)]
     lib.fdtd_batch_set_chi.argtypes = [vp, vp, vp, i64, vp]
     lib.fdtd_batch_sample_pe.argtypes = [vp, i64, vp, vp]
+    lib.fdtd_solve_noalloc.argtypes = [P, i64, vp, vp, vp]
     _lib = lib
     return lib
 
@@ -135,6 +140,25 @@ def describe(inst) -> dict:
     if rc:
         raise FdtdError(rc, lib.fdtd_last_error(None).decode())
     return json.loads(buf.value.decode())
+
+
+def solve_noalloc(inst, n_rows: int, pe_out=None, row_out=None, stream=None) -> None:
+    """fdtd_solve_noalloc: boundary, march of n_rows rows and the readouts of
+    P_e (into the float64 device tensor pe_out, n_rows+1 values) and of row
+    n_rows (into the device tensor row_out, Nx+1 complex values) in the
+    library's own device workspace; enqueued on `stream` (torch's current
+    stream by default).  Raises FdtdError on failure."""
+    import torch
+    lib = load()
+    p = params(inst)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib.fdtd_solve_noalloc(ctypes.byref(p), int(n_rows),
+                                ctypes.c_void_p(pe_out.data_ptr()) if pe_out is not None else None,
+                                ctypes.c_void_p(row_out.data_ptr()) if row_out is not None else None,
+                                ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise FdtdError(rc, lib.fdtd_last_error(None).decode())
 
 
 class Solver:
