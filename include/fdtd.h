@@ -51,7 +51,8 @@ enum fdtd_status {
     FDTD_ESIZE = -2,    /* workspace too small, or an output buffer too short */
     FDTD_ESTATE = -3,   /* call out of order (march before boundary), or a row no longer held */
     FDTD_EDEVICE = -4,  /* a HIP runtime error */
-    FDTD_ERANGE = -5    /* gamma(n,z) series out of range, or a non-finite boundary value */
+    FDTD_ERANGE = -5    /* gamma(n,z) series out of range, a non-finite boundary value, or a non-finite
+                           value (NaN or infinity) in the march */
 };
 
 /* Incident states (Table 1 "init_cond" 1-3, plus a Gaussian two-photon packet). */
@@ -122,7 +123,11 @@ int fdtd_set_boundary_tables(fdtd_ctx *ctx, const double *h_E, int64_t n);
 
 /* Advance the march by n_rows rows (resumable: the row counter lives in the
  * context).  Rows past Nt are not marched (FDTD_ESTATE).  Returns after
- * enqueueing the work. */
+ * enqueueing the work, which ends with a check of the rows just marched for
+ * non-finite values: every value the march writes enters the per-row sums of
+ * |psi|^2, and a NaN or infinity there sets the context's status, which
+ * fdtd_sync and readouts into host memory report as FDTD_ERANGE (until the
+ * next fdtd_set_boundary). */
 int fdtd_march(fdtd_ctx *ctx, int64_t n_rows);
 
 /* Current row (the last row solved; 0 right after set_boundary). */
@@ -154,7 +159,8 @@ enum fdtd_readout_kind {
 
 /* Copy a readout into dst: a device pointer (dst_on_device = 1, enqueued on
  * the context's stream) or a host pointer (dst_on_device = 0; the call then
- * waits for the stream).  Complex outputs are (re, im) pairs. */
+ * waits for the stream, and returns FDTD_ERANGE, with the values copied, if
+ * the march met a non-finite value).  Complex outputs are (re, im) pairs. */
 int fdtd_readout(fdtd_ctx *ctx, int32_t what, int64_t arg, void *dst, int64_t count, int32_t dst_on_device);
 
 /* Checkpoint and restore of a march (its state is the workspace: the ring
@@ -171,7 +177,8 @@ int fdtd_checkpoint_size(const fdtd_ctx *ctx, size_t *bytes);
 int fdtd_checkpoint(fdtd_ctx *ctx, void *h_dst, size_t bytes);
 int fdtd_restore(fdtd_ctx *ctx, const void *h_src, size_t bytes);
 
-/* Wait for all work of this context. */
+/* Wait for all work of this context; FDTD_ERANGE if the march met a
+ * non-finite value. */
 int fdtd_sync(fdtd_ctx *ctx);
 
 /* Free the context (not the workspace).  Accepts NULL. */
@@ -280,7 +287,7 @@ int fdtd_batch_sample_pe(fdtd_batch *b, int64_t n_samples, const double *d_t_end
 /* Launches of one march, and workgroups of the first (largest) launch. */
 int fdtd_batch_info(const fdtd_batch *b, int64_t *launches, int64_t *max_workgroups);
 
-int fdtd_batch_sync(fdtd_batch *b);
+int fdtd_batch_sync(fdtd_batch *b);      /* FDTD_ERANGE if any instance's march met a non-finite value */
 int fdtd_batch_destroy(fdtd_batch *b);   /* frees host state and the graph, not the workspace; accepts NULL */
 const char *fdtd_batch_last_error(const fdtd_batch *b);
 

@@ -358,6 +358,15 @@ static int check_status(fdtd_ctx* c)
     return FDTD_OK;
 }
 
+// the march's part of the status word
+static int march_status(fdtd_ctx* c, int st)
+{
+    if (st & STATUS_MARCH_NONFINITE)
+        return fail(c, FDTD_ERANGE, "non-finite value (NaN or infinity) in the march, rows 1..%lld",
+                    (long long)c->row);
+    return FDTD_OK;
+}
+
 int fdtd_set_boundary(fdtd_ctx* c)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
@@ -406,6 +415,7 @@ constexpr int64_t MU_ROWS = 256;
 static int march_to(fdtd_ctx* c, int64_t target)
 {
     const int64_t T = c->plan.T, Nt = c->p.Nt, R = c->g.R;
+    const int64_t first = c->row + 1;                 // rows this call completes: first..target
     int64_t p0 = -1, p1 = -1;                 // rows waiting for their mu sums
     auto flush = [&]() -> int {
         if (p0 < 0) return FDTD_OK;
@@ -443,7 +453,11 @@ static int march_to(fdtd_ctx* c, int64_t target)
         c->row = m1;
         if (s1 >= s0) c->strip_row = s1;
     }
-    return flush();
+    int rc = flush();
+    if (rc) return rc;
+    // a NaN or infinity anywhere in the rows just marched sets the status word
+    // (reported by fdtd_sync and by readouts into host memory)
+    return launch_check_rows(c, first, target);
 }
 
 int fdtd_march(fdtd_ctx* c, int64_t n_rows)
@@ -536,10 +550,12 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         return fail(c, FDTD_EINVAL, "unknown readout %d", what);
     }
     if (rc) return fail(c, rc, "readout launch failed");
+    int st = 0;
     hipError_t e = hipMemcpyAsync(dst, src, (size_t)count * esz, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "readout copy failed: %s", hipGetErrorString(e));
-    return FDTD_OK;
+    return march_status(c, st);
 }
 
 // checkpoint: a header, then the context's workspace (ring, diagonal copy,
@@ -619,9 +635,11 @@ int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
 int fdtd_sync(fdtd_ctx* c)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
-    hipError_t e = hipStreamSynchronize(c->stream);
+    int st = 0;
+    hipError_t e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "%s", hipGetErrorString(e));
-    return FDTD_OK;
+    return march_status(c, st);
 }
 
 int fdtd_destroy(fdtd_ctx* c)

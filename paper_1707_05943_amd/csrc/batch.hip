@@ -24,6 +24,7 @@ struct fdtd_batch {
     OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
     int n_ode = 0;
     ChiJob* d_jobs = nullptr;        // chi snapshots, sorted by the launch after which they are taken
+    int* d_status = nullptr;         // the batch's status word (non-finite values in any instance's march)
     std::vector<int> job_begin;      // per launch k: first job, and one past the last (job_begin[k+1])
     int64_t chi_ntau = 0;
     std::vector<int> n_active;       // per launch k: instances still marching
@@ -90,7 +91,7 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
 {
     const PlanKnobs kn = knobs_of(o);
     int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst)) + al256((int64_t)n * (int64_t)sizeof(OdeInst)) +
-                al256((int64_t)n * (int64_t)sizeof(ChiJob));
+                al256((int64_t)n * (int64_t)sizeof(ChiJob)) + 256;
     for (int i = 0; i < n; ++i) {
         int rc = ctx_validate(&p[i], kn, why, nwhy);
         if (rc) {
@@ -116,7 +117,8 @@ static void destroy(fdtd_batch* b)
 }
 
 // the launches of the batch from launch k0 to k1-1 on stream s, each
-// followed by the chi snapshots whose row it completes
+// followed by the chi snapshots whose row it completes; a march that reaches
+// the last launch ends with the non-finite check of every instance
 static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
 {
     for (int64_t k = k0; k < k1 && k < b->Lmax; ++k) {
@@ -128,6 +130,7 @@ static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
             if (rc) return rc;
         }
     }
+    if (k1 >= b->Lmax) return launch_check_batch(b->d_tab, b->n, b->d_status, s);
     return FDTD_OK;
 }
 
@@ -185,6 +188,8 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     off += al256((int64_t)n * (int64_t)sizeof(OdeInst));
     b->d_jobs = (ChiJob*)(base + off);
     off += al256((int64_t)n * (int64_t)sizeof(ChiJob));
+    b->d_status = (int*)(base + off);
+    off += 256;
     for (int i = 0; i < n; ++i) {
         const int64_t sz = ctx_bytes(&p[i], kn);
         fdtd_ctx* c = nullptr;
@@ -244,6 +249,7 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
         e = hipMemcpyAsync(b->d_ode + b->n_ode, c->d_ode, sizeof(OdeInst), hipMemcpyDeviceToDevice, b->stream);
         ++b->n_ode;
     }
+    if (e == hipSuccess && launch_clear_status(b->d_status, b->stream)) e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         destroy(b);
@@ -257,6 +263,7 @@ int fdtd_batch_set_boundary(fdtd_batch* b)
 {
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     b->state = 0;
+    if (launch_clear_status(b->d_status, b->stream)) return bfail(b, FDTD_EDEVICE, "status clear failed");
     for (int i = 0; i < b->n; ++i) {
         fdtd_ctx* c = b->c[i];
         if (c->p.boundary == FDTD_E_DELAY_ODE) {
@@ -402,8 +409,13 @@ int fdtd_batch_info(const fdtd_batch* b, int64_t* launches, int64_t* max_workgro
 int fdtd_batch_sync(fdtd_batch* b)
 {
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
-    hipError_t e = hipStreamSynchronize(b->stream);
+    int st = 0;
+    hipError_t e = hipMemcpyAsync(&st, b->d_status, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "%s", hipGetErrorString(e));
+    if (st & STATUS_MARCH_NONFINITE)
+        return bfail(b, FDTD_ERANGE, "non-finite value (NaN or infinity) in the march of an instance "
+                     "(fdtd_batch_readout names it)");
     return FDTD_OK;
 }
 

@@ -157,7 +157,9 @@ struct fdtd_ctx {
     char err[512];
 };
 
-enum { STATUS_GAMMA_RANGE = 1, STATUS_NONFINITE = 2 };
+// device status word of a context (cleared with the boundary): gamma series
+// out of range, a non-finite boundary value, a non-finite value in the march
+enum { STATUS_GAMMA_RANGE = 1, STATUS_NONFINITE = 2, STATUS_MARCH_NONFINITE = 4 };
 
 // launch helpers implemented in the .hip files
 int launch_boundary(fdtd_ctx* c, int from_host_E);
@@ -171,6 +173,10 @@ int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst);
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst);
 int launch_clear(fdtd_ctx* c);
+// non-finite detection over the per-row partial sums of |psi|^2 of rows
+// r0..r1 (every marched value enters them): sets STATUS_MARCH_NONFINITE
+int launch_check_rows(fdtd_ctx* c, int64_t r0, int64_t r1);
+int launch_clear_status(int* st, hipStream_t s);
 // non-Markovian measures of stimulated emission: e0(t_r) into c->E0; the
 // partial sums of mu over rows r0..r1 (complete rows of the ring); the
 // readouts mu(t_r) and lambda(t_r) for r < nrows
@@ -233,6 +239,9 @@ struct BInst {
 };
 
 int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipStream_t s);
+// the same check over every row of every instance of a batch (each
+// instance's status word, and `batch_status` for the whole batch)
+int launch_check_batch(const BInst* d_tab, int n, int* batch_status, hipStream_t s);
 
 // A chi snapshot of one instance at row `row`, detector separations
 // k * stride * Delta for k < n_tau (zero beyond the last column).

@@ -84,6 +84,42 @@ __global__ void k_pe_sample(const BInst* __restrict__ tab, int64_t ns, const dou
     dst[e.index * ns + k] = (1.0 - f) * p[0] + f * p[1];
 }
 
+// Non-finite detection.  Every value the march writes enters the per-row,
+// per-workgroup partial sums of |psi|^2, so a NaN or an infinity anywhere in
+// a row makes one of that row's sums non-finite.  Entries lo..hi-1 of Ppart.
+__device__ inline int nonfinite_in(const double* __restrict__ Ppart, int64_t lo, int64_t hi, int64_t i0,
+                                   int64_t stride)
+{
+    int bad = 0;
+    for (int64_t i = lo + i0; i < hi; i += stride) bad |= !isfinite(Ppart[i]);
+    return bad;
+}
+
+__global__ void k_check_rows(const double* __restrict__ Ppart, int64_t lo, int64_t hi, int* status)
+{
+    const int bad = __syncthreads_or(nonfinite_in(Ppart, lo, hi, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                                                  (int64_t)gridDim.x * blockDim.x));
+    if (bad && threadIdx.x == 0) atomicOr(status, STATUS_MARCH_NONFINITE);
+}
+
+// every row of instance blockIdx.y of a batch
+__global__ void k_check_batch(const BInst* __restrict__ tab, int* batch_status)
+{
+    const BInst& e = tab[blockIdx.y];
+    const int64_t hi = (e.g.Nt + 1) * (int64_t)e.P.nwg;
+    const int bad = __syncthreads_or(nonfinite_in(e.b.Ppart, 0, hi, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                                                  (int64_t)gridDim.x * blockDim.x));
+    if (bad && threadIdx.x == 0) {
+        atomicOr(e.b.status, STATUS_MARCH_NONFINITE);
+        atomicOr(batch_status, STATUS_MARCH_NONFINITE);
+    }
+}
+
+__global__ void k_clear_word(int* st)
+{
+    if (threadIdx.x == 0) *st = 0;
+}
+
 __global__ void k_row_copy(Geom g, Bufs b, int64_t rho, cd* dst)
 {
     int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -131,5 +167,28 @@ int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst)
 {
     hipLaunchKernelGGL(k_row_copy, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b,
                        rho, dst);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_check_rows(fdtd_ctx* c, int64_t r0, int64_t r1)
+{
+    if (r1 < r0) return FDTD_OK;
+    const int64_t lo = r0 * c->nblk, hi = (r1 + 1) * c->nblk;
+    int64_t blocks = (hi - lo + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_check_rows, dim3((unsigned)blocks), dim3(256), 0, c->stream, c->b.Ppart, lo, hi,
+                       c->b.status);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_check_batch(const BInst* d_tab, int n, int* batch_status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_batch, dim3(16, (unsigned)n), dim3(256), 0, s, d_tab, batch_status);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_clear_status(int* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, s, st);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
