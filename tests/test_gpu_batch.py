@@ -13,7 +13,7 @@ from paper_1707_05943_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
-FLOOR = 0.1
+FLOOR = 0.01
 
 
 def _say(msg):
@@ -50,9 +50,8 @@ def batch_cases():
 
 def _oracle(inst):
     """the oracle's run of `inst` with the row at the peak of P_e kept: rows
-    that have decayed below 10% of that row are measured against 10% of it
-    (the scheme's amplification factor is -1 at k Delta = pi, so grid-scale
-    rounding noise is not damped while the field decays)"""
+    that have decayed below 1% of that row are measured against 1% of it
+    (their own rounding noise, ~1e-16 of the peak per row, is what remains)"""
     E = oracle.E_table(inst)
     pre = oracle.march(inst, E, want_ring=False)["pe"]
     rp = int(np.argmax(pre)) if np.all(np.isfinite(pre)) else inst.Nt // 2
@@ -65,20 +64,23 @@ def _compare_instance(bat, i, inst, ref, label):
     """last D+2 rows and P_e of instance i against the oracle run `ref`"""
     scale = ref["scale"]
     R = inst.D + 2
-    worst = 0.0
+    worst = own = 0.0
     for q in range(R):
         rho = inst.Nt - (R - 1) + q
         if rho < 0:
             continue
         got = bat.row_values(i, rho)
-        e = np.linalg.norm(got - ref["ring"][q]) / max(np.linalg.norm(ref["ring"][q]), FLOOR * scale, 1e-300)
+        d, n = np.linalg.norm(got - ref["ring"][q]), np.linalg.norm(ref["ring"][q])
+        e = d / max(n, FLOOR * scale, 1e-300)
         worst = max(worst, e)
+        own = max(own, d / n if n > 0 else 0.0)
         assert e <= TOL, (label, inst.name, "row", rho, e)
     if inst.incident != W.INC_PLANE:
         pe = bat.pe(i)
         e = np.linalg.norm(pe - ref["pe"]) / np.linalg.norm(ref["pe"])
         assert e <= TOL, (label, inst.name, "P_e", e)
         worst = max(worst, e)
+    _say(f"[batch] {label} {inst.name}: worst row error against its own norm {own:.2e}")
     return worst
 
 
@@ -230,3 +232,60 @@ def test_batch_lambda_of_stimulated_emission():
         bat.lam(1)
     assert err.value.code == -1
     bat.close()
+
+
+# Instances of the 512-instance sweep draw (seed 7) checked inside the full,
+# autotuned batch, as the benchmark runs it: (index, rows compared).  The
+# oracle's E (direct quadrature of the delay series) costs O(Nt^2 / D), so
+# the extremes with long windows are compared on a row prefix (P_e and E of
+# rows 0..prefix depend on nothing later); two mid-range instances in full
+# (their last D+2 rows as well).
+SWEEP_PICKS = [
+    (205, 1024),        # smallest D (18), Nx 1024, boundary over 57 round trips
+    (144, 2048),        # largest |alpha| (0.084): the recurrence's longest horizon
+    (179, 2 * 4960 + 600),   # largest D (4960), Nx 16384: the widest instance
+    (139, 2 * 4084 + 600),   # largest D/Nx (0.4985)
+    (300, None),        # D 894, Nx 2048, Nt 8192: in full
+    (100, None),        # D 942, Nx 4096, Nt 16384: in full
+]
+
+
+def test_sweep_draw_instances_in_the_full_batch():
+    """The benchmark's batched sweep -- 512 seed-drawn instances, autotuned
+    tiles, one captured graph -- and six of its instances against the oracle
+    (the batch's E comes from the delay equation, the oracle's from the
+    quadrature of the delay series)."""
+    import torch
+    insts = W.sweep_draw(512, 7)
+    refs = {}
+    for k, prefix in SWEEP_PICKS:
+        inst = insts[k]
+        ref_inst = inst if prefix is None else W.with_sizes(inst, Nt=prefix)
+        _say(f"[batch] oracle for sweep instance {k}: D={inst.D} Nx={inst.Nx} Nt={inst.Nt} rows {ref_inst.Nt}")
+        refs[k] = (ref_inst, _oracle(ref_inst) if prefix is None else
+                   oracle.march(ref_inst, oracle.E_table(ref_inst), want_ring=False))
+    dev = torch.device("cuda:0")
+    need = max(fdtd.batch_workspace_size(insts, fdtd.batch_opts(t, w)) for t in (32, 16, 8) for w in (0, 768))
+    _say(f"[batch] autotune over the 512 instances ({need / 1e9:.0f} GB workspace)")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    best, rate = fdtd.autotune(insts, probe_rows=256, workspace=ws)
+    _say(f"[batch] autotuned tmax={best.tmax} wmax={best.wmax}; marching the batch")
+    bat = fdtd.Batch(insts, best, workspace=ws).set_boundary().march()
+    bat.sync()
+    for k, prefix in SWEEP_PICKS:
+        inst = insts[k]
+        ref_inst, ref = refs[k]
+        n = ref_inst.Nt + 1
+        c = math.sqrt(2.0) * np.exp(1j * inst.phase)
+        got_E = bat.E(k)[:n] / c
+        eE = np.max(np.abs(got_E - ref["E"])) / np.max(np.abs(ref["E"]))
+        pe = bat.pe(k)[:n]
+        ePe = np.linalg.norm(pe - ref["pe"]) / np.linalg.norm(ref["pe"])
+        _say(f"[batch] sweep instance {k}: E {eE:.2e}, P_e over rows 0..{n - 1} {ePe:.2e}")
+        assert eE <= TOL and ePe <= TOL, (k, eE, ePe)
+        if prefix is None:
+            w = _compare_instance(bat, k, inst, ref, "sweep draw")
+            assert w <= TOL
+    bat.close()
+    del ws
+    torch.cuda.empty_cache()
