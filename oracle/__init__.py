@@ -50,7 +50,9 @@ class OrcParams(ctypes.Structure):
                 ("incident", ctypes.c_int32), ("pad0", ctypes.c_int32),
                 ("k", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("x0", ctypes.c_double), ("width", ctypes.c_double),
-                ("phase", ctypes.c_double)]
+                ("phase", ctypes.c_double), ("identical", ctypes.c_int32), ("pad1", ctypes.c_int32),
+                ("k1", ctypes.c_double), ("k2", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double)]
 
 
 def _load():
@@ -72,6 +74,10 @@ def _load():
     lib.orc_E_table.argtypes = [P(OrcParams), ctypes.c_int, vp]
     lib.orc_march.argtypes = [P(OrcParams), vp, vp, vp, vp, i64, i64, vp, vp, i64, vp]
     lib.orc_march.restype = ctypes.c_int
+    lib.orc_chi0_arr.argtypes = [P(OrcParams), i64, vp, vp, vp]
+    lib.orc_exact_part_arr.argtypes = [P(OrcParams), vp, vp]
+    lib.orc_two_photon_A.argtypes = [P(OrcParams)]
+    lib.orc_two_photon_A.restype = ctypes.c_double
     _lib = lib
     return lib
 
@@ -83,7 +89,15 @@ def params(inst) -> OrcParams:
                      omega0=float(d["omega0"]), Gamma=float(d["Gamma"]), incident=int(d["incident"]),
                      pad0=0, k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
                      x0=float(d.get("x0", 0.0)), width=float(d.get("width", 1.0)),
-                     phase=float(d.get("phase", 0.0)))
+                     phase=float(d.get("phase", 0.0)), identical=int(d.get("identical_photons", 1)), pad1=0,
+                     k1=float(d.get("k1", 0.0)), k2=float(d.get("k2", 0.0)),
+                     alpha1=float(d.get("alpha1", 0.0)), alpha2=float(d.get("alpha2", 0.0)))
+
+
+def two_photons(inst) -> bool:
+    """two different exponential photons (Sec. 2 case (c) with identical_photons = 0)"""
+    d = inst if isinstance(inst, dict) else inst.as_dict()
+    return int(d["incident"]) == 3 and int(d.get("identical_photons", 1)) == 0
 
 
 def _ptr(a: np.ndarray):
@@ -163,10 +177,11 @@ def phi_mass_below(inst, y):
 def E_table(inst, mode: int = 0) -> np.ndarray:
     """E(t_r) for r = 0..Nt.  mode 0: closed form where the paper gives one,
     quadrature of the delay series for the Gaussian; mode 1: quadrature on the
-    grid for every family; mode 2: quadrature evaluated row by row."""
+    grid for every family; mode 2: quadrature evaluated row by row.  Two
+    different photons: e0^(1)(t_r) followed by e0^(2)(t_r) (2 (Nt+1) values)."""
     lib = _load()
     p = params(inst)
-    out = np.empty(int(p.Nt) + 1, np.complex128)
+    out = np.empty((2 if two_photons(inst) else 1) * (int(p.Nt) + 1), np.complex128)
     lib.orc_E_table(ctypes.byref(p), int(mode), _ptr(out))
     return out
 
@@ -186,7 +201,7 @@ def march(inst, E: np.ndarray | None = None, *, chi_rows=(), n_tau: int = 0, sna
     if E is None:
         E = E_table(inst)
     E = np.ascontiguousarray(E, dtype=np.complex128)
-    assert E.shape == (p.Nt + 1,)
+    assert E.shape == ((2 if two_photons(inst) else 1) * (p.Nt + 1),)
     C = p.Nx + 1
     R = p.D + 2
     pe = np.empty(p.Nt + 1, np.float64) if want_pe else None
@@ -203,3 +218,29 @@ def march(inst, E: np.ndarray | None = None, *, chi_rows=(), n_tau: int = 0, sna
     if rc != 0:
         raise RuntimeError(f"oracle march failed ({rc}): a read broke the ring's lag bound")
     return {"E": E, "pe": pe, "ring": ring, "chi": chi, "snaps": snaps}
+
+
+def chi0(inst, x1, x2):
+    """the initial two-photon state chi(x1, x2, 0), global phase included"""
+    lib = _load()
+    p = params(inst)
+    x1, x2 = np.broadcast_arrays(_tarr(x1), _tarr(x2))
+    x1, x2 = np.ascontiguousarray(x1), np.ascontiguousarray(x2)
+    out = np.empty(x1.shape, np.complex128)
+    lib.orc_chi0_arr(ctypes.byref(p), x1.size, _ptr(x1), _ptr(x2), _ptr(out))
+    return out
+
+
+def exact_part(inst, E) -> np.ndarray:
+    """int_{-inf}^{-a} |psi(x, t_r)|^2 dx of the exact solution, r = 0..Nt"""
+    lib = _load()
+    p = params(inst)
+    E = np.ascontiguousarray(E, dtype=np.complex128)
+    out = np.empty(int(p.Nt) + 1, np.float64)
+    lib.orc_exact_part_arr(ctypes.byref(p), _ptr(E), _ptr(out))
+    return out
+
+
+def two_photon_A(inst) -> float:
+    """the normalisation constant A of Eq. (11)"""
+    return float(_load().orc_two_photon_A(ctypes.byref(params(inst))))

@@ -163,6 +163,9 @@ typedef struct {
     double k, alpha;        /* carrier; exponential width in units of Gamma */
     double x0, width;       /* Gaussian centre and std of |phi|^2 */
     double phase;           /* global phase of the two-photon state */
+    int32_t identical;      /* 0: two different exponential photons (Sec. 2 case (c), Table 1) */
+    int32_t pad1;
+    double k1, k2, alpha1, alpha2;   /* photon 1 and photon 2 when identical = 0 */
 } orc_params;
 
 static double half_a(const orc_params *p) { return 0.5 * (double)p->D * p->Delta; }
@@ -188,6 +191,46 @@ cplx orc_phi(const orc_params *p, double x)
     }
     }
     return NAN;
+}
+
+/* ---- two different photons (Sec. 2 case (c)) ----
+ * chi(x1, x2, 0) = (A/sqrt 2) [phi1(x1) phi2(x2) + phi1(x2) phi2(x1)] (Eq. 10),
+ * phi_i the packet of Eq. (7) with (k_i, alpha_i), A of Eq. (11); in x <= -a
+ * psi(x, t) = A [phi1(x-t) e0^(2)(t) + phi2(x-t) e0^(1)(t)] (Eq. 12), e0^(i)
+ * the one-excitation amplitude driven by phi_i (Eq. 13).  A global phase
+ * e^{i theta} multiplies the whole state, as for the other families. */
+static int two_photons(const orc_params *p) { return p->incident == INC_EXP2 && !p->identical; }
+
+/* photon i (1 or 2) as a one-packet parameter set */
+static orc_params photon(const orc_params *p, int i)
+{
+    orc_params q = *p;
+    q.identical = 1;
+    q.k = (i == 1) ? p->k1 : p->k2;
+    q.alpha = (i == 1) ? p->alpha1 : p->alpha2;
+    return q;
+}
+
+/* Eq. (11) */
+static double two_photon_A(const orc_params *p)
+{
+    double dk = p->k1 - p->k2, s = (p->alpha1 + p->alpha2) * p->Gamma;
+    double num = 4.0 * dk * dk + s * s;
+    return sqrt(num / (num + 4.0 * p->alpha1 * p->alpha2 * p->Gamma * p->Gamma));
+}
+
+/* the initial two-photon state chi(x1, x2, 0) of every two-photon family,
+ * global phase included (zero for stimulated emission) */
+cplx orc_chi0(const orc_params *p, double x1, double x2)
+{
+    cplx eth = cexp(I * p->phase);
+    if (p->incident == INC_EXP1) return 0.0;
+    if (two_photons(p)) {
+        orc_params a = photon(p, 1), b = photon(p, 2);
+        return eth * two_photon_A(p) / sqrt(2.0) *
+               (orc_phi(&a, x1) * orc_phi(&b, x2) + orc_phi(&a, x2) * orc_phi(&b, x1));
+    }
+    return eth * orc_phi(p, x1) * orc_phi(p, x2);
 }
 
 /* closed form Eq. (6): plane wave, A = 1 */
@@ -424,9 +467,17 @@ static void E_table_quad(const orc_params *p, cplx *E)
 }
 
 /* E(t_r), r = 0..Nt: the closed form where the paper gives one, else the
- * quadrature of the delay series.  mode 0: default, 1: force quadrature. */
+ * quadrature of the delay series.  mode 0: default, 1: force quadrature (on
+ * the grid), 2: quadrature row by row.  Two different photons: e0^(1) in
+ * E[0..Nt], then e0^(2) in E[Nt+1..2Nt+1]. */
 void orc_E_table(const orc_params *p, int mode, cplx *E)
 {
+    if (two_photons(p)) {
+        orc_params a = photon(p, 1), b = photon(p, 2);
+        orc_E_table(&a, mode, E);
+        orc_E_table(&b, mode, E + (p->Nt + 1));
+        return;
+    }
     for (int64_t r = 0; r <= p->Nt; ++r) {
         double t = (double)r * p->Delta;
         if (mode == 0 && p->incident != INC_GAUSS2) E[r] = orc_E_closed(p, t);
@@ -441,9 +492,12 @@ void orc_E_table(const orc_params *p, int mode, cplx *E)
 
 typedef struct {
     const orc_params *p;
-    const cplx *E;           /* E(t_r), r = 0..Nt */
-    const cplx *phig;        /* phi(-a - q Delta), q = 0..Nt: phi at the grid points x - t of x <= -a */
-    cplx c_ex;               /* psi = c_ex phi(x-t) E(t) in x <= -a */
+    const cplx *E;           /* E(t_r), r = 0..Nt (two different photons: e0^(1)) */
+    const cplx *phig;        /* phi(-a - q Delta), q = 0..Nt: phi at the grid points x - t of x <= -a
+                                (two different photons: phi1) */
+    const cplx *E2;          /* two different photons: e0^(2)(t_r); else NULL */
+    const cplx *phig2;       /* two different photons: phi2(-a - q Delta); else NULL */
+    cplx c_ex;               /* psi = c_ex phi(x-t) E(t) in x <= -a (two photons: c_ex [phi1 e0^(2) + phi2 e0^(1)]) */
     cplx *ring;              /* (D+2) rows of Nx+1 columns; row rho in slot rho mod (D+2) */
     int64_t cur;             /* row being solved */
     int fault;               /* set when a read violates the ring's lag bound */
@@ -454,6 +508,7 @@ typedef struct {
  * x_i - t_rho = -a - (rho - i) Delta */
 static cplx psi_exact(const orc_state *s, int64_t i, int64_t rho)
 {
+    if (s->E2) return s->c_ex * (s->phig[rho - i] * s->E2[rho] + s->phig2[rho - i] * s->E[rho]);
     return s->c_ex * s->phig[rho - i] * s->E[rho];
 }
 
@@ -487,7 +542,8 @@ static cplx bar(orc_state *s, int64_t i, int64_t rho)
  *       and their space argument midway between two columns
  *   drive (line 4) -> chi(x-t, -/+a - t, 0) evaluated at the centre.  */
 static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1, r) */,
-                       cplx drive_row /* phi(-a - t_c) - phi(a - t_c) */)
+                       cplx drive_row /* phi(-a - t_c) - phi(a - t_c) */,
+                       cplx drive_row2 /* two photons: the same for phi2 (drive_row is phi1's) */)
 {
     const orc_params *p = s->p;
     const int64_t D = p->D;
@@ -518,7 +574,11 @@ static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1,
     /* drive: sqrt(G) [chi0(x-t, -a-t) - chi0(x-t, a-t)] at the centre, where
      * x_c - t_c = x_j - t_r lies on the grid (phi there is phig[r - j]) and
      * phi(-a - t_c), phi(a - t_c) are the same for the whole row */
-    if (p->incident != INC_EXP1 && r - j >= 0)
+    if (s->E2 && r - j >= 0)
+        /* chi0(xi, y) = e^{i theta} (A/sqrt 2) [phi1(xi) phi2(y) + phi2(xi) phi1(y)] */
+        rhs += sqrt(G) * cexp(I * p->phase) * two_photon_A(p) / sqrt(2.0) *
+               (s->phig[r - j] * drive_row2 + s->phig2[r - j] * drive_row);
+    else if (p->incident != INC_EXP1 && r - j >= 0)
         rhs += sqrt(G) * cexp(I * p->phase) * s->phig[r - j] * drive_row;
     (void)a; (void)dl;
     /* (U - bl)/Delta + (W/4)(bl + br + tl + U) = rhs */
@@ -536,7 +596,10 @@ static cplx chi_detector(orc_state *s, int64_t r, int64_t kk)
     const int64_t j1 = D + 1, j2 = D + 1 + kk;
     /* chi(x1 - t, x2 - t, 0) = e^{i theta} phi(x1 - t) phi(x2 - t); x_j - t_r = -a - (r - j) Delta */
     cplx c0 = 0.0;
-    if (p->incident != INC_EXP1 && r - j1 >= 0 && r - j2 >= 0)
+    if (s->E2 && r - j1 >= 0 && r - j2 >= 0)
+        c0 = cexp(I * p->phase) * two_photon_A(p) / sqrt(2.0) *
+             (s->phig[r - j1] * s->phig2[r - j2] + s->phig[r - j2] * s->phig2[r - j1]);
+    else if (p->incident != INC_EXP1 && r - j1 >= 0 && r - j2 >= 0)
         c0 = cexp(I * p->phase) * s->phig[r - j1] * s->phig[r - j2];
     (void)a; (void)dl;
     cplx acc = 0.0;
@@ -567,12 +630,40 @@ static double phi_mass_below(const orc_params *p, double y)
     return NAN;   /* plane wave: not normalisable */
 }
 
+/* two exponential photons: int_{-inf}^{y} conj(phi1) phi2 for y <= -a.  With
+ * v = u + a the integrand is sqrt(alpha1 alpha2) G e^{-i(k2-k1)a} e^{c v},
+ * c = i(k2 - k1) + (alpha1 + alpha2) G/2 (Eq. 7 for both photons). */
+static cplx phi_cross_below(const orc_params *p, double y)
+{
+    double a = half_a(p), G = p->Gamma;
+    if (y > -a) y = -a;
+    cplx c = I * (p->k2 - p->k1) + 0.5 * (p->alpha1 + p->alpha2) * G;
+    return sqrt(p->alpha1 * p->alpha2) * G * cexp(-I * (p->k2 - p->k1) * a) * cexp(c * (y + a)) / c;
+}
+
+/* int_{-inf}^{-a} |psi(x, t_r)|^2 dx from the exact solution: |c E|^2 times
+ * the packet's mass below -a - t, and for two different photons
+ * A^2 [|e2|^2 m11 + |e1|^2 m22 + 2 Re(conj(e2) e1 m12)] with m_ij the mass of
+ * conj(phi_i) phi_j below -a - t */
+static double exact_part(const orc_state *s, int64_t r)
+{
+    const orc_params *p = s->p;
+    double y = -half_a(p) - r * p->Delta;
+    if (s->E2) {
+        orc_params a = photon(p, 1), b = photon(p, 2);
+        double A = two_photon_A(p);
+        cplx e1 = s->E[r], e2 = s->E2[r];
+        return A * A * (creal(e2 * conj(e2)) * phi_mass_below(&a, y) + creal(e1 * conj(e1)) * phi_mass_below(&b, y)
+                        + 2.0 * creal(conj(e2) * e1 * phi_cross_below(p, y)));
+    }
+    double cc = (p->incident == INC_EXP1) ? 1.0 : 2.0;
+    return cc * creal(s->E[r] * conj(s->E[r])) * phi_mass_below(p, y);
+}
+
 static double pe_row(orc_state *s, int64_t r)
 {
     const orc_params *p = s->p;
-    double t = r * p->Delta;
-    double cc = (p->incident == INC_EXP1) ? 1.0 : 2.0;
-    double ex = cc * creal(s->E[r] * conj(s->E[r])) * phi_mass_below(p, -half_a(p) - t);
+    double ex = exact_part(s, r);
     double acc = 0.0;
     for (int64_t j = 0; j <= p->Nx; ++j) {
         cplx v = psi_at(s, j, r);
@@ -598,13 +689,23 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
               const int64_t *snap_rows, int64_t n_snap, cplx *snaps)
 {
     const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt, R = D + 2, C = Nx + 1;
-    orc_state s = { p, E, NULL, 0.0, NULL, 0, 0 };
+    const int two = two_photons(p);
+    orc_params ph1 = two ? photon(p, 1) : *p, ph2 = two ? photon(p, 2) : *p;
+    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0 };
     s.ring = (cplx *)calloc((size_t)(R * C), sizeof(cplx));
-    cplx *phig = (cplx *)malloc(sizeof(cplx) * (size_t)(Nt + 1));
+    cplx *phig = (cplx *)malloc(sizeof(cplx) * (size_t)(2 * (Nt + 1)));
     if (!s.ring || !phig) { free(s.ring); free(phig); return -2; }
-    for (int64_t q = 0; q <= Nt; ++q) phig[q] = orc_phi(p, -half_a(p) - (double)q * p->Delta);
+    for (int64_t q = 0; q <= Nt; ++q) {
+        phig[q] = orc_phi(&ph1, -half_a(p) - (double)q * p->Delta);
+        phig[Nt + 1 + q] = orc_phi(&ph2, -half_a(p) - (double)q * p->Delta);
+    }
     s.phig = phig;
     s.c_ex = (p->incident == INC_EXP1) ? 1.0 : sqrt(2.0) * cexp(I * p->phase);
+    if (two) {
+        s.phig2 = phig + (Nt + 1);
+        s.E2 = E + (Nt + 1);
+        s.c_ex = two_photon_A(p) * cexp(I * p->phase);
+    }
 
     /* row 0: psi(x, 0) = 0 for x > -a in every family */
     s.cur = 0;
@@ -622,9 +723,10 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
         row[0] = 0.0;              /* column 0 is read from the exact solution */
         cplx left = psi_at(&s, 0, r);
         double tc = ((double)r - 0.5) * p->Delta;
-        cplx drive_row = orc_phi(p, -half_a(p) - tc) - orc_phi(p, half_a(p) - tc);
+        cplx drive_row = orc_phi(&ph1, -half_a(p) - tc) - orc_phi(&ph1, half_a(p) - tc);
+        cplx drive_row2 = orc_phi(&ph2, -half_a(p) - tc) - orc_phi(&ph2, half_a(p) - tc);
         for (int64_t j = 1; j <= Nx; ++j) {
-            cplx u = solve_cell(&s, j, r, left, drive_row);
+            cplx u = solve_cell(&s, j, r, left, drive_row, drive_row2);
             row[j] = u;
             left = u;
         }
@@ -652,6 +754,7 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
 
 /* thin exports used by the tests */
 cplx orc_phi_at(const orc_params *p, double x) { return orc_phi(p, x); }
+double orc_two_photon_A(const orc_params *p) { return two_photon_A(p); }
 double orc_phi_mass_below(const orc_params *p, double y) { return phi_mass_below(p, y); }
 
 /* ======================================================================
@@ -695,4 +798,19 @@ void orc_phi_arr(const orc_params *p, int64_t m, const double *x, cplx *out)
 void orc_phi_mass_below_arr(const orc_params *p, int64_t m, const double *y, double *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = phi_mass_below(p, y[i]);
+}
+
+void orc_chi0_arr(const orc_params *p, int64_t m, const double *x1, const double *x2, cplx *out)
+{
+    for (int64_t i = 0; i < m; ++i) out[i] = orc_chi0(p, x1[i], x2[i]);
+}
+
+/* int_{-inf}^{-a} |psi(x, t_r)|^2 dx of the exact solution for rows r = 0..Nt
+ * (E as for orc_march) */
+void orc_exact_part_arr(const orc_params *p, const cplx *E, double *out)
+{
+    const int64_t Nt = p->Nt;
+    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0 };
+    if (two_photons(p)) s.E2 = E + (Nt + 1);
+    for (int64_t r = 0; r <= Nt; ++r) out[r] = exact_part(&s, r);
 }

@@ -27,7 +27,14 @@ import numpy as np
 
 
 class Micro:
-    def __init__(self, inst, E: np.ndarray, phi, *, mode: str = "hybrid", diag_cols: int = 0):
+    """E and phi: the one-excitation amplitude on the rows and the packet.
+    Two different photons (Sec. 2 case (c)): phi and E are photon 1's packet
+    and e0^(1), phi2 and E2 photon 2's; then chi(x1, x2, 0) =
+    (A/sqrt 2)[phi(x1) phi2(x2) + phi(x2) phi2(x1)] and, in x <= -a,
+    psi = A [phi(x-t) E2(t) + phi2(x-t) E(t)], with A of Eq. (11)."""
+
+    def __init__(self, inst, E: np.ndarray, phi, *, mode: str = "hybrid", diag_cols: int = 0,
+                 phi2=None, E2: np.ndarray | None = None):
         d = inst if isinstance(inst, dict) else inst.as_dict()
         self.Nx, self.D, self.Nt = int(d["Nx"]), int(d["D"]), int(d["Nt"])
         self.dl = float(d["Delta"])
@@ -44,6 +51,14 @@ class Micro:
         self.done_row = 0                  # rows <= done_row are complete
         self.cur = (0, 0)                  # cell being solved (row, col)
         self.c_ex = 1.0 if self.incident == 2 else math.sqrt(2.0) * complex(math.cos(self.theta_ph), math.sin(self.theta_ph))
+        self.phi2 = phi2
+        self.E2 = None if E2 is None else np.asarray(E2, dtype=np.complex128)
+        if phi2 is not None:
+            k1, k2 = float(d["k1"]), float(d["k2"])
+            a1, a2 = float(d["alpha1"]), float(d["alpha2"])
+            num = 4 * (k1 - k2) ** 2 + ((a1 + a2) * self.G) ** 2
+            self.A = math.sqrt(num / (num + 4 * a1 * a2 * self.G ** 2))
+            self.c_ex = self.A * complex(math.cos(self.theta_ph), math.sin(self.theta_ph))
 
     # ---- grid <-> coordinates -------------------------------------------
     def col(self, x: float) -> int:
@@ -62,6 +77,8 @@ class Micro:
     def exact(self, i: int, r: int) -> complex:
         x = -self.a + i * self.dl
         t = r * self.dl
+        if self.phi2 is not None:
+            return self.c_ex * (self.phi(x - t) * self.E2[r] + self.phi2(x - t) * self.E[r])
         return self.c_ex * self.phi(x - t) * self.E[r]
 
     def value(self, x: float, t: float) -> complex:
@@ -79,6 +96,8 @@ class Micro:
         if self.incident == 2:
             return 0.0
         ph = complex(math.cos(self.theta_ph), math.sin(self.theta_ph))
+        if self.phi2 is not None:
+            return ph * self.A / math.sqrt(2.0) * (self.phi(x1) * self.phi2(x2) + self.phi(x2) * self.phi2(x1))
         return ph * self.phi(x1) * self.phi(x2)
 
     # ---- Eq. (3) and Eq. (4) --------------------------------------------
@@ -171,13 +190,32 @@ class Micro:
 
         return self.chi0(x1 - t, x2 - t) - math.sqrt(G) / 2.0 * (part(x1, x2) + part(x2, x1))
 
+    def exact_mass(self, r: int, x_edge: float, depth: float) -> float:
+        """int_{x_edge - depth}^{x_edge} |psi_exact(x, t_r)|^2 dx by composite
+        20-point Gauss-Legendre (for states without a closed form at hand)."""
+        t = r * self.dl
+        xg, wg = np.polynomial.legendre.leggauss(20)
+        edges = np.linspace(x_edge - depth, x_edge, 401)
+        tot = 0.0
+        for u, v in zip(edges[:-1], edges[1:]):
+            for xq, wq in zip(0.5 * (u + v) + 0.5 * (v - u) * xg, wg):
+                y = xq - t
+                val = self.c_ex * (self.phi(y) * self.E2[r] + self.phi2(y) * self.E[r])
+                tot += 0.5 * (v - u) * wq * abs(val) ** 2
+        return tot
+
     def pe(self, r: int, phi_mass_below) -> float:
         """int |psi(x, t_r)|^2 dx: the exact part left of the marched columns in
         closed form (|c E|^2 times the packet's mass), plus the trapezoid rule
-        over the columns from the first marched one's left neighbour to Nx."""
+        over the columns from the first marched one's left neighbour to Nx.
+        Two different photons: phi_mass_below is the depth of the quadrature
+        of the exact part instead (see exact_mass)."""
         t = r * self.dl
         x_edge = -self.a + (self.lo - 1) * self.dl
-        ex = abs(self.c_ex * self.E[r]) ** 2 * phi_mass_below(x_edge - t)
+        if self.phi2 is not None:
+            ex = self.exact_mass(r, x_edge, float(phi_mass_below))
+        else:
+            ex = abs(self.c_ex * self.E[r]) ** 2 * phi_mass_below(x_edge - t)
         vals = [self.at(i, r) for i in range(self.lo - 1, self.Nx + 1)]
         m2 = np.abs(np.asarray(vals)) ** 2
         return ex + self.dl * (m2.sum() - 0.5 * m2[0] - 0.5 * m2[-1])

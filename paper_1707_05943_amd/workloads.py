@@ -25,7 +25,7 @@ import numpy as np
 # incident families (Table 1 init_cond 1-3, plus the Gaussian packet)
 INC_PLANE = 1      # two-photon plane wave, Eqs. (5)-(6)
 INC_EXP1 = 2       # stimulated emission: one exponential photon, emitter excited, Eqs. (7)-(9)
-INC_EXP2 = 3       # two identical exponential photons, Eqs. (10)-(13)
+INC_EXP2 = 3       # two exponential photons, Eqs. (10)-(13) (identical, or different: identical_photons = 0)
 INC_GAUSS2 = 4     # two identical Gaussian photons
 
 
@@ -46,6 +46,11 @@ class Instance:
     phase: float = 0.0      # global phase theta of the two-photon state
     seed: int = 0
     boundary: int = 0       # how the library computes E(t_r): 0 delay series, 1 delay equation
+    identical_photons: int = 1   # 0: two different exponential photons (k1, alpha1), (k2, alpha2) (Table 1)
+    k1: float = 0.0
+    k2: float = 0.0
+    alpha1: float = 0.0
+    alpha2: float = 0.0
     extra: dict = field(default_factory=dict)
 
     @property
