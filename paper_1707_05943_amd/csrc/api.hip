@@ -34,6 +34,7 @@ static void coefficients(const fdtd_params* p, Geom* g)
     g->alpha = (-0.25 * W) * g->cinv;
     g->cB = g->alpha;
     g->cA = (mk(1.0 / p->Delta, 0.0) - 0.25 * W) * g->cinv;
+    g->cAm1 = (-0.5 * W) * g->cinv;
 }
 
 // columns recomputed left of a block so that the dropped term alpha^halo U is

@@ -56,6 +56,8 @@ struct Geom {
     cd W;               // i omega0 + Gamma/2
     cd alpha;           // coefficient of psi(j-1, r) in the solved square
     cd cA;              // coefficient of psi(j-1, r-1)
+    cd cAm1;            // cA - 1 = -(W/2) cinv, formed directly: the march adds psi(j-1, r-1) + cAm1 psi(j-1, r-1),
+                        // so the rounding of cA ~ 1 is not applied anew at every step of a characteristic
     cd cB;              // coefficient of psi(j, r-1)
     cd cinv;            // 1/(1/Delta + W/4)
     int halo;           // columns recomputed left of a block for the within-row recurrence

@@ -5,6 +5,9 @@
 //
 //   psi(j, r) = alpha psi(j-1, r) + beta(j, r)
 //   beta      = cA psi(j-1, r-1) + cB psi(j, r-1) + cinv S
+//             = psi(j-1, r-1) + [(cA - 1) psi(j-1, r-1) + cB psi(j, r-1) + cinv S]
+// (the second form is the one evaluated: cA is close to 1, and its rounding
+// would otherwise enter once per row along every characteristic)
 //   S         = (G/8)[psi(j-1-D, r-1-D) + psi(j-D, r-1-D) + psi(j-1-D, r-D) + psi(j-D, r-D)]   (r-1 >= D)
 //               - (G/2)[bar(-j, r-j) - bar(D-j, r-j)]                                        (r-j >= 0)
 //               - (G/2)[bar(2D-j, r-j+D) - bar(D-j, r-j+D)]                                  (j > D, r-j+D >= 0)
@@ -318,7 +321,7 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
     const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
     const bool live = j0 <= jmax;
     const unsigned own = (unsigned)(j0 * 16);                 // byte offset of column j0 in a row
-    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd al = g.alpha, cAm1 = g.cAm1, cB = g.cB;
     cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
                                                               // prologue's barrier (the set-up writes them)
     const cd* tE = S.tE;
@@ -394,8 +397,8 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
         #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t j = j0 + i;
-            cd v = zero();
-            cmac(v, cA, up[i]);
+            cd v = up[i];                                     // cA psi(j-1, r-1) = psi(j-1, r-1) + cAm1 psi(j-1, r-1)
+            cmac(v, cAm1, up[i]);
             cmac(v, cB, up[i + 1]);
             cmac(v, g8r, p[i] + p[i + 1]);
             const int64_t t = live ? t0 - i : 0;
@@ -457,7 +460,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     const int64_t jmax = (S.hi - 1 < g.Nx) ? S.hi - 1 : g.Nx;
     const bool live = j0 <= jmax;
     const unsigned own = (unsigned)(j0 * 16);
-    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd al = g.alpha, cAm1 = g.cAm1, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
     cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
                                                               // prologue's barrier (the set-up writes them)
@@ -585,8 +588,8 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             const bool cell = (j >= act_lo && j <= jmax);
             const int64_t t = live ? t0 - i : 0;
             const cd et = tE[t], ph = tP[t], et2 = tE2[t];
-            cd v = zero();
-            cmac(v, cA, up[i]);
+            cd v = up[i];                                     // cA psi(j-1, r-1) = psi(j-1, r-1) + cAm1 psi(j-1, r-1)
+            cmac(v, cAm1, up[i]);
             cmac(v, cB, up[i + 1]);
             cmac(v, g8r, p[i] + p[i + 1]);
             cmac(v, krc, et);                           // first source, exact
@@ -660,7 +663,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     const int64_t j0 = S.lo + (int64_t)K * (tid - S.t0);
     const int64_t jmax = (S.hi - 1 < D) ? S.hi - 1 : D;
     const bool live = j0 <= jmax;
-    const cd al = g.alpha, cA = g.cA, cB = g.cB;
+    const cd al = g.alpha, cAm1 = g.cAm1, cB = g.cB;
     const cd c4 = (0.25 * g.Gamma) * g.cinv;
     cd ap[K], lp;                                             // alpha^(i+1), alpha^(K lane): read after the
                                                               // prologue's barrier (the set-up writes them)
@@ -763,8 +766,8 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             t = t < 1 ? 1 : t;                        // cells past the range read a valid entry, then drop out
             const cd pq = tP[t], pm = tP[t - 1], pp = tP[t + 1];
             const cd et = tE[t];
-            cd v = zero();
-            cmac(v, cA, up[i]);
+            cd v = up[i];                                     // cA psi(j-1, r-1) = psi(j-1, r-1) + cAm1 psi(j-1, r-1)
+            cmac(v, cAm1, up[i]);
             cmac(v, cB, up[i + 1]);
             cmac(v, ga, pq + pm);
             cmac(v, gb, pp + pq);

@@ -62,23 +62,40 @@ MARCH_CASES = {
 }
 
 
-FLOOR = 0.1
+FLOOR = 0.01
+# chi of Eq. (2) is a difference of psi values: after the packet has passed it
+# cancels to far below the values it is formed from (in the |alpha| = 0.47
+# case below, to 2e-9 of its peak while psi stays at 0.36 of its own), and
+# two valid evaluation orders of the scheme then differ by 1.3e-12 of 1% of
+# chi's peak (the oracle with its own cell update and with the library's,
+# on the CPU); chi is measured against 10% of its peak instead
+CHI_FLOOR = 0.1
+_UNFLOORED = {"worst": 0.0}
 
 
 def _row_err(got, ref, scale):
-    """relative L2 of a row.  Rows that have decayed below 10% of the run's
-    largest row are measured against 10% of that row: the square scheme's
-    amplification factor (App. A) is exactly -1 at k Delta = pi, so rounding
-    noise on the grid scale is not damped while the solution decays, and the
-    two sides' noise (~1e-16 of the peak per row) is what remains there."""
-    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), FLOOR * scale)
+    """relative L2 of a row.  Rows that have decayed below 1% of the run's
+    largest row are measured against 1% of that row (their own rounding
+    noise, ~1e-16 of the peak per row, is what remains there).  The error
+    against the row's own norm is recorded as well and printed."""
+    d = np.linalg.norm(got - ref)
+    n = np.linalg.norm(ref)
+    if n > 0:
+        _UNFLOORED["worst"] = max(_UNFLOORED["worst"], d / n)
+    return d / max(n, FLOOR * scale)
+
+
+def _unfloored_reset():
+    w = _UNFLOORED["worst"]
+    _UNFLOORED["worst"] = 0.0
+    return w
 
 
 def march_and_compare(inst, sol, E, rows, n_tau, label):
     """March the library to each of `rows` in turn and compare the row and the
     chi readout there with the oracle; then the final ring (D+2 rows) and
     P_e(t_r) over every row."""
-    # always compare around the peak of P_e too, so that the 1% floor is
+    # always compare around the peak of P_e too, so that the floor is
     # taken from rows where the field is alive
     pre = oracle.march(inst, E, want_ring=False)["pe"]
     if np.all(np.isfinite(pre)):
@@ -98,11 +115,12 @@ def march_and_compare(inst, sol, E, rows, n_tau, label):
         if n_tau:
             got = sol.chi(n_tau)
             cs = max(np.linalg.norm(c) for c in ref["chi"])
-            e = np.linalg.norm(got - ref["chi"][q]) / max(np.linalg.norm(ref["chi"][q]), FLOOR * cs)
+            e = np.linalg.norm(got - ref["chi"][q]) / max(np.linalg.norm(ref["chi"][q]), CHI_FLOOR * cs)
             assert e <= TOL, (label, "chi", r, e)
     # the same rows as one space-time field
     e_all = rel_l2(np.concatenate(got_rows), np.concatenate(list(ref["snaps"])))
-    _say(f"[parity] {label}: worst row {worst:.2e}, space-time rel-L2 {e_all:.2e}")
+    _say(f"[parity] {label}: worst row {worst:.2e} (against its own norm {_unfloored_reset():.2e}), "
+         f"space-time rel-L2 {e_all:.2e}")
     assert e_all <= TOL, (label, "space-time", e_all)
     R = inst.D + 2
     for q in range(R):
@@ -196,27 +214,41 @@ def test_small_gauss_end_to_end():
 
 
 def test_large_gauss_column_window():
-    """D=10000, Nx=262144 marched on the GPU for D+600 rows (delay and both
-    source terms active, 256 blocks).  The scheme is chiral -- column j
-    depends on columns <= j only -- so the oracle run on the first 2D+1100
-    columns must reproduce those columns of the full-width GPU run."""
+    """D=10000, Nx=262144 marched on the GPU for 2D+600 rows in the launch
+    configuration the benchmark times (256 workgroups of 32-row blocks): the
+    delay, both source terms and the delay of delayed values (rows past
+    2D+1) are active.  The scheme is chiral -- column j depends on columns
+    <= j only -- so the oracle run on the first 2D+4000 columns must
+    reproduce those columns of the full-width GPU run; they span the strip's
+    27 workgroups, the near part's 27 and the first four far workgroups
+    (boundaries at columns 20192, 21408, 22624 and 23840)."""
     big = W.large_gauss()
-    rows = big.D + 600
+    rows = 2 * big.D + 600
     gpu_inst = W.with_sizes(big, Nt=rows)
-    win = W.with_sizes(big, Nx=2 * big.D + 1100, Nt=rows)
-    _say(f"[parity] column window of {big.name}: rows={rows} window={win.Nx}")
+    win = W.with_sizes(big, Nx=2 * big.D + 4000, Nt=rows)
+    plan = fdtd.describe(gpu_inst)
+    starts = [plan["near_end"] + 1 + f * plan["far_w"] for f in range(4)]
+    assert starts[-1] < win.Nx, (starts, win.Nx)
+    _say(f"[parity] column window of {big.name}: rows={rows} window={win.Nx} far workgroups from {starts}")
     E = oracle.E_table(win)
     ref = oracle.march(win, E)
+    _say("[parity] oracle done")
     sol = fdtd.Solver(gpu_inst).set_boundary()
     got_E = sol.E() / (math.sqrt(2.0) * np.exp(1j * big.phase))
     assert np.max(np.abs(got_E - E)) <= TOL * np.max(np.abs(E))
     sol.march(rows)
+    first = rows - (win.D + 1)                  # the oracle's ring holds rows first..rows
     scale = max(np.linalg.norm(v) for v in ref["ring"])
-    for q in (0, 1, win.D // 2, win.D, win.D + 1):
-        rho = rows - (win.D + 1) + q
+    check = [first, first + 1, 15000, 2 * big.D + 1, 2 * big.D + 2, 2 * big.D + 300, rows - 1, rows]
+    for rho in check:
         got = sol.row_values(rho)[: win.Nx + 1]
-        e = _row_err(got, ref["ring"][q], scale)
+        e = _row_err(got, ref["ring"][rho - first], scale)
         assert e <= TOL, ("row", rho, e)
+        # each far workgroup's columns on their own
+        for c0, c1 in zip([big.D + 1] + starts, starts + [win.Nx + 1]):
+            d = np.linalg.norm(got[c0:c1] - ref["ring"][rho - first][c0:c1])
+            assert d <= TOL * max(np.linalg.norm(ref["ring"][rho - first][c0:c1]), FLOOR * scale), (rho, c0, d)
+    _say(f"[parity] {big.name} window: worst row against its own norm {_unfloored_reset():.2e}")
     sol.close()
 
 
@@ -241,6 +273,7 @@ def test_paper_parameter_sets_column_window(name):
         got = sol.row_values(rho)[: win.Nx + 1]
         e = _row_err(got, ref["ring"][q], scale)
         assert e <= TOL, ("row", rho, e)
+    _say(f"[parity] paper set {name}: worst row against its own norm {_unfloored_reset():.2e}")
     sol.close()
 
 
