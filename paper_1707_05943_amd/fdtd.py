@@ -71,6 +71,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FdtdError(-4, f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own libamdhip64 under the
+    # same soname, which its libraries load by file name.  Loading torch first
+    # makes this library bind to that copy; loaded the other way round the
+    # process would hold two runtimes and one of them would see no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     P = ctypes.POINTER(FdtdParams)
