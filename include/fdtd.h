@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 1u
+#define FDTD_ABI_VERSION 2u
 
 enum fdtd_status {
     FDTD_OK = 0,
@@ -59,7 +59,8 @@ enum fdtd_status {
 enum fdtd_incident {
     FDTD_INC_PLANE = 1,  /* two-photon plane wave e^{ik(x1+x2)}, Eqs. (5)-(6), A = 1 */
     FDTD_INC_EXP1 = 2,   /* stimulated emission: one exponential photon, emitter excited, Eqs. (7)-(9) */
-    FDTD_INC_EXP2 = 3,   /* two identical exponential photons, Eqs. (10)-(13) */
+    FDTD_INC_EXP2 = 3,   /* two exponential photons, Eqs. (10)-(13): identical (k, alpha), or with
+                            identical_photons = 0 two different ones (k1, alpha1), (k2, alpha2) */
     FDTD_INC_GAUSS2 = 4  /* two identical Gaussian photons, phi ~ exp(-(x-x0)^2/(4 w^2) + i k (x-x0)) for x <= -a */
 };
 
@@ -95,6 +96,13 @@ typedef struct fdtd_params {
     double x0;              /* Gaussian centre (x0 <= -a) */
     double width;           /* Gaussian: standard deviation of |phi|^2 */
     double phase;           /* global phase theta of the incident two-photon state */
+    int32_t identical_photons; /* Table 1: 1 (the usual case) for identical photons; 0 for two different
+                                  exponential photons (FDTD_INC_EXP2 only): then the incident state is
+                                  (A/sqrt 2)[phi1(x1) phi2(x2) + phi1(x2) phi2(x1)] (Eq. 10, A of Eq. 11),
+                                  phi_i of Eq. (7) with (k_i, alpha_i), and k, alpha are not used */
+    int32_t reserved;       /* must be 0 */
+    double k1, k2;          /* carriers of photon 1 and photon 2 (identical_photons = 0) */
+    double alpha1, alpha2;  /* widths of photon 1 and photon 2, units of Gamma (identical_photons = 0) */
 } fdtd_params;
 
 typedef struct fdtd_ctx fdtd_ctx;
@@ -118,7 +126,8 @@ int fdtd_init(const fdtd_params *p, void *d_workspace, size_t bytes, void *hip_s
 int fdtd_set_boundary(fdtd_ctx *ctx);
 
 /* Test hook: as fdtd_set_boundary, but E(t_r) (r = 0..n-1, n = Nt+1) is
- * copied from the caller's host array of complex doubles (n pairs). */
+ * copied from the caller's host array of complex doubles (n pairs); for two
+ * different photons n = 2 (Nt+1): e0^(1)(t_r) followed by e0^(2)(t_r). */
 int fdtd_set_boundary_tables(fdtd_ctx *ctx, const double *h_E, int64_t n);
 
 /* Advance the march by n_rows rows (resumable: the row counter lives in the
@@ -141,7 +150,8 @@ enum fdtd_readout_kind {
     FDTD_RO_CHI = 3,   /* chi(x1, x2, t) of Eq. (2) at the current row, detectors x1 = a + Delta,
                           x2 = x1 + k Delta for k = 0..count-1 (count <= Nx-D) */
     FDTD_RO_E = 4,     /* the boundary table c E(t_r), r = 0..count-1 (count <= Nt+1); c = sqrt(2) e^{i theta}
-                          for two photons, 1 for stimulated emission */
+                          for two identical photons, 1 for stimulated emission; two different photons:
+                          A e^{i theta} e0^(1) (arg = 0) or A e^{i theta} e0^(2) (arg = 1) */
     /* Non-Markovian measures of stimulated emission (App. D; FDTD_INC_EXP1 contexts only, else
        FDTD_EINVAL).  e0(t) is the emitter amplitude of the one-excitation problem with the same
        packet and the emitter initially in its ground state, phi(x,t) = phi_in(x-t)

@@ -74,7 +74,22 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
         snprintf(why, n, "unknown incident family %d", p->incident);
         return FDTD_EINVAL;
     }
-    if ((p->incident == FDTD_INC_EXP1 || p->incident == FDTD_INC_EXP2) && !(p->alpha > 0.0)) {
+    if (p->identical_photons != 0 && p->identical_photons != 1) {
+        snprintf(why, n, "identical_photons must be 0 or 1");
+        return FDTD_EINVAL;
+    }
+    if (p->reserved != 0) { snprintf(why, n, "reserved must be 0"); return FDTD_EINVAL; }
+    if (p->identical_photons == 0) {
+        if (p->incident != FDTD_INC_EXP2) {
+            snprintf(why, n, "two different photons are defined for the exponential family (FDTD_INC_EXP2) only");
+            return FDTD_EINVAL;
+        }
+        if (!isfinite(p->k1) || !isfinite(p->k2) || !(p->alpha1 > 0.0) || !(p->alpha2 > 0.0) ||
+            !isfinite(p->alpha1) || !isfinite(p->alpha2)) {
+            snprintf(why, n, "two different photons need finite k1, k2 and alpha1, alpha2 > 0");
+            return FDTD_EINVAL;
+        }
+    } else if ((p->incident == FDTD_INC_EXP1 || p->incident == FDTD_INC_EXP2) && !(p->alpha > 0.0)) {
         snprintf(why, n, "exponential packets need alpha > 0");
         return FDTD_EINVAL;
     }
@@ -195,32 +210,42 @@ static int plan_for(const fdtd_params* p, const PlanKnobs& kn, Plan* P, char* wh
     return make_plan(p, halo_for(g.alpha), kn, P, why, n);
 }
 
+static int two_photons(const fdtd_params* p) { return p->incident == FDTD_INC_EXP2 && p->identical_photons == 0; }
+
+// a context's workspace: one march, or for two different photons two marches
+// and the row sums of |psi_a + psi_b|^2
+static int64_t ctx_total(const fdtd_params* p, const Plan& P)
+{
+    const int64_t one = layout(p, P).total;
+    if (!two_photons(p)) return one;
+    return 2 * one + align256((p->Nt + 1) * PAIR_CHUNKS * 8);
+}
+
 int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn)
 {
     char why[256];
     Plan P;
     if (plan_for(p, kn, &P, why, sizeof why)) return -1;
-    return layout(p, P).total;
+    return ctx_total(p, P);
 }
 
-// Fill the context *c (caller's storage) for parameters p over the caller's
-// workspace, and enqueue the clearing of the ring and the copies of the
-// boundary's step weights (waits for them).  Allocates nothing.
-static int ctx_setup(fdtd_ctx* c, const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes,
-                     hipStream_t stream, char* why, size_t nwhy)
+// A of Eq. (11): chi(x1, x2, 0) = (A/sqrt 2)[phi1(x1) phi2(x2) + phi1(x2) phi2(x1)] has unit norm
+static double two_photon_A(const fdtd_params* p)
 {
-    int rc = ctx_validate(p, kn, why, nwhy);
-    if (rc) return rc;
-    Plan P;
-    plan_for(p, kn, &P, why, nwhy);
-    const int64_t nblk = P.nwg;
-    Layout L = layout(p, P);
-    if (!d_workspace || bytes < (size_t)L.total) {
-        snprintf(why, nwhy, "workspace of %zu bytes is smaller than the %lld needed", bytes, (long long)L.total);
-        return FDTD_ESIZE;
-    }
-    if (((uintptr_t)d_workspace) & 255) { snprintf(why, nwhy, "workspace must be 256-byte aligned"); return FDTD_EINVAL; }
+    const double dk = p->k1 - p->k2, s = (p->alpha1 + p->alpha2) * p->Gamma;
+    const double num = 4.0 * dk * dk + s * s;
+    return sqrt(num / (num + 4.0 * p->alpha1 * p->alpha2 * p->Gamma * p->Gamma));
+}
 
+// One march in *c over the workspace at `base` (layout L): photon 0 for the
+// one-packet families; for two different photons 2 (march a: photon 2's e0
+// and drive) or 1 (march b: photon 1's).  Enqueues the clearing of the ring
+// and the copies of the boundary's step weights and waits for them.
+static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const Layout& L, char* base, int photon,
+                       hipStream_t stream, char* why, size_t nwhy)
+{
+    const int64_t nblk = P.nwg;
+    int rc = FDTD_OK;
     memset(c, 0, sizeof *c);
     c->p = *p;
     c->stream = stream;
@@ -239,12 +264,19 @@ static int ctx_setup(fdtd_ctx* c, const fdtd_params* p, const PlanKnobs& kn, voi
     if (p->incident == FDTD_INC_EXP1) {
         pk.c_ex = mk(1.0, 0.0);      // Eq. (8): psi = phi(x-t) e1(t)
         pk.c_drive = mk(0.0, 0.0);   // no two-photon component
+    } else if (photon) {
+        // Eq. (12): psi = A e^{i theta} [phi1(x-t) e0^(2)(t) + phi2(x-t) e0^(1)(t)]; this march takes one
+        // packet's e0 and drive (Eq. 10's chi0 in line 4 of Eq. 1), the other packet's phi on the x - t grid
+        const double A = two_photon_A(p);
+        pk.k = photon == 1 ? p->k1 : p->k2;
+        pk.alpha = photon == 1 ? p->alpha1 : p->alpha2;
+        pk.c_ex = A * eth;
+        pk.c_drive = (sqrt(p->Gamma) * A / sqrt(2.0)) * eth;
     } else {
         pk.c_ex = sqrt(2.0) * eth;   // Eq. (12), identical photons: sqrt(2) phi(x-t) E(t)
         pk.c_drive = sqrt(p->Gamma) * eth;
     }
 
-    char* base = (char*)d_workspace;
     Bufs& b = c->b;
     b.ring = (cd*)(base + L.ring);
     b.Md = (cd*)(base + L.Md);
@@ -291,6 +323,36 @@ static int ctx_setup(fdtd_ctx* c, const fdtd_params* p, const PlanKnobs& kn, voi
     return FDTD_OK;
 }
 
+// Fill the context *c (caller's storage; for two different photons also
+// *pair, march b) for parameters p over the caller's workspace.  Allocates
+// nothing.
+static int ctx_setup(fdtd_ctx* c, fdtd_ctx* pair, const fdtd_params* p, const PlanKnobs& kn, void* d_workspace,
+                     size_t bytes, hipStream_t stream, char* why, size_t nwhy)
+{
+    int rc = ctx_validate(p, kn, why, nwhy);
+    if (rc) return rc;
+    Plan P;
+    plan_for(p, kn, &P, why, nwhy);
+    const Layout L = layout(p, P);
+    const int64_t total = ctx_total(p, P);
+    if (!d_workspace || bytes < (size_t)total) {
+        snprintf(why, nwhy, "workspace of %zu bytes is smaller than the %lld needed", bytes, (long long)total);
+        return FDTD_ESIZE;
+    }
+    if (((uintptr_t)d_workspace) & 255) { snprintf(why, nwhy, "workspace must be 256-byte aligned"); return FDTD_EINVAL; }
+    const int two = two_photons(p);
+    if (two && !pair) { snprintf(why, nwhy, "two different photons need the second march's context"); return FDTD_EINVAL; }
+    char* base = (char*)d_workspace;
+    rc = march_setup(c, p, P, L, base, two ? 2 : 0, stream, why, nwhy);
+    if (rc || !two) return rc;
+    rc = march_setup(pair, p, P, L, base + L.total, 1, stream, why, nwhy);
+    if (rc) return rc;
+    c->pair = pair;
+    c->xpart = (double*)(base + 2 * L.total);
+    c->c0_pair = (two_photon_A(p) / sqrt(2.0)) * mk(cos(p->phase), sin(p->phase));
+    return FDTD_OK;
+}
+
 int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes, hipStream_t stream,
                fdtd_ctx** out, char* why, size_t nwhy)
 {
@@ -299,9 +361,16 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
     if (!out) { snprintf(why, nwhy, "out is NULL"); return FDTD_EINVAL; }
     *out = nullptr;
     fdtd_ctx* c = (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx));
-    if (!c) { snprintf(why, nwhy, "out of host memory"); return FDTD_EDEVICE; }
-    rc = ctx_setup(c, p, kn, d_workspace, bytes, stream, why, nwhy);
+    fdtd_ctx* pair = two_photons(p) ? (fdtd_ctx*)calloc(1, sizeof(fdtd_ctx)) : nullptr;
+    if (!c || (two_photons(p) && !pair)) {
+        free(c);
+        free(pair);
+        snprintf(why, nwhy, "out of host memory");
+        return FDTD_EDEVICE;
+    }
+    rc = ctx_setup(c, pair, p, kn, d_workspace, bytes, stream, why, nwhy);
     if (rc) {
+        free(pair);
         free(c);
         return rc;
     }
@@ -348,12 +417,54 @@ int fdtd_init(const fdtd_params* p, void* d_workspace, size_t bytes, void* hip_s
     return FDTD_OK;
 }
 
+// enqueue the copy of the status word(s) into st[0..1] (the second march's
+// for two different photons, else 0); the caller waits for the stream
+static hipError_t status_copy(fdtd_ctx* c, int* st)
+{
+    st[0] = st[1] = 0;
+    hipError_t e = hipMemcpyAsync(&st[0], c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && c->pair)
+        e = hipMemcpyAsync(&st[1], c->pair->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    return e;
+}
+
+// the boundary of one march, or of both marches of two different photons:
+// march a takes photon 2's e0 and drive but photon 1's packet on the x - t
+// grid, march b the reverse, so each march's boundary kernels write their phi
+// table into the other march's; then the exact part of P_e (with the
+// packets' cross term) and row 0's sum of |psi_a + psi_b|^2
+static int boundary_enqueue(fdtd_ctx* c, int from_host)
+{
+    if (!c->pair) return launch_boundary(c, from_host);
+    fdtd_ctx* m[2] = {c, c->pair};
+    for (int i = 0; i < 2; ++i) {
+        fdtd_ctx t = *m[i];
+        t.b.Phi = m[1 - i]->b.Phi;
+        int rc = launch_boundary(&t, from_host);
+        if (rc) return rc;
+    }
+    int rc = launch_pex_pair(c);
+    if (!rc) rc = launch_pair_rows(c, 0, 0);
+    return rc;
+}
+
+static void boundary_done(fdtd_ctx* c)
+{
+    for (fdtd_ctx* m = c; m; m = (m == c) ? c->pair : nullptr) {
+        m->row = 0;
+        m->strip_row = 0;
+        m->mu_row = m->mupart ? 0 : -1;
+        m->boundary_ready = 1;
+    }
+}
+
 static int check_status(fdtd_ctx* c)
 {
-    int st = 0;
-    hipError_t e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    int sts[2];
+    hipError_t e = status_copy(c, sts);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+    const int st = sts[0] | sts[1];
     if (st & STATUS_GAMMA_RANGE) return fail(c, FDTD_ERANGE, "gamma(n,z) series out of range");
     if (st & STATUS_NONFINITE) return fail(c, FDTD_ERANGE, "non-finite boundary value");
     return FDTD_OK;
@@ -371,31 +482,32 @@ static int march_status(fdtd_ctx* c, int st)
 int fdtd_set_boundary(fdtd_ctx* c)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
-    int rc = launch_boundary(c, 0);
+    int rc = boundary_enqueue(c, 0);
     if (rc) return fail(c, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
     rc = check_status(c);
     if (rc) return rc;
-    c->row = 0;
-    c->strip_row = 0;
-    c->mu_row = c->mupart ? 0 : -1;
-    c->boundary_ready = 1;
+    boundary_done(c);
     return FDTD_OK;
 }
 
 int fdtd_set_boundary_tables(fdtd_ctx* c, const double* h_E, int64_t n)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
-    if (!h_E || n != c->p.Nt + 1) return fail(c, FDTD_ESIZE, "expected Nt+1 = %lld values", (long long)(c->p.Nt + 1));
-    hipError_t e = hipMemcpyAsync(c->b.Ebuf, h_E, (size_t)n * 16, hipMemcpyHostToDevice, c->stream);
+    const int64_t n1 = c->p.Nt + 1;
+    if (!h_E || n != (c->pair ? 2 : 1) * n1)
+        return fail(c, FDTD_ESIZE, "expected %s%lld values", c->pair ? "2 (Nt+1) = " : "Nt+1 = ",
+                    (long long)((c->pair ? 2 : 1) * n1));
+    // two different photons: e0^(1) then e0^(2); march a takes e0^(2), march b e0^(1)
+    hipError_t e = hipMemcpyAsync(c->b.Ebuf, h_E + (c->pair ? 2 * n1 : 0), (size_t)n1 * 16, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess && c->pair)
+        e = hipMemcpyAsync(c->pair->b.Ebuf, h_E, (size_t)n1 * 16, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "copy of E failed: %s", hipGetErrorString(e));
-    int rc = launch_boundary(c, 1);
+    int rc = boundary_enqueue(c, 1);
     if (rc) return fail(c, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
     rc = check_status(c);
     if (rc) return rc;
-    c->row = 0;
-    c->strip_row = 0;
-    c->mu_row = c->mupart ? 0 : -1;
-    c->boundary_ready = 1;
+    boundary_done(c);
     return FDTD_OK;
 }
 
@@ -417,14 +529,23 @@ static int march_to(fdtd_ctx* c, int64_t target)
 {
     const int64_t T = c->plan.T, Nt = c->p.Nt, R = c->g.R;
     const int64_t first = c->row + 1;                 // rows this call completes: first..target
-    int64_t p0 = -1, p1 = -1;                 // rows waiting for their mu sums
+    int64_t p0 = -1, p1 = -1;     // complete rows waiting for their row sums (mu; |psi_a + psi_b|^2)
     auto flush = [&]() -> int {
         if (p0 < 0) return FDTD_OK;
-        int rc = launch_mu_rows(c, p0, p1, c->stream);
+        int rc = FDTD_OK;
+        if (c->mupart) rc = launch_mu_rows(c, p0, p1, c->stream);
+        if (!rc && c->pair) rc = launch_pair_rows(c, p0, p1);
         if (rc) return rc;
-        c->mu_row = p1;
+        if (c->mupart) c->mu_row = p1;
         p0 = p1 = -1;
         return FDTD_OK;
+    };
+    // a launch of the march, and of the second march of two different photons
+    // (the same plan: the two advance in lock step)
+    auto block = [&](int64_t a0, int64_t a1, int64_t b0, int64_t b1) -> int {
+        int rc = launch_block(c, a0, a1, b0, b1);
+        if (!rc && c->pair) rc = launch_block(c->pair, a0, a1, b0, b1);
+        return rc;
     };
     while (c->row < target) {
         const int64_t m0 = 1 + T * (c->row / T);
@@ -439,14 +560,14 @@ static int march_to(fdtd_ctx* c, int64_t target)
         }
         if (strip_only) {
             // the strip must hold every row this block reads: march it alone first
-            int rc = launch_block(c, 1, 0, s0, s1);
+            int rc = block(1, 0, s0, s1);
             if (rc) return rc;
             c->strip_row = s1;
             continue;
         }
-        int rc = launch_block(c, m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
+        int rc = block(m0, m1, s1 >= s0 ? s0 : 1, s1 >= s0 ? s1 : 0);
         if (rc) return rc;
-        if (c->mupart) {
+        if (c->mupart || c->pair) {
             if (p0 < 0) p0 = m0;
             p1 = m1;
             if (p1 - p0 + 1 >= MU_ROWS && (rc = flush())) return rc;
@@ -458,7 +579,13 @@ static int march_to(fdtd_ctx* c, int64_t target)
     if (rc) return rc;
     // a NaN or infinity anywhere in the rows just marched sets the status word
     // (reported by fdtd_sync and by readouts into host memory)
-    return launch_check_rows(c, first, target);
+    rc = launch_check_rows(c, first, target);
+    if (!rc && c->pair) {
+        c->pair->row = c->row;
+        c->pair->strip_row = c->strip_row;
+        rc = launch_check_rows(c->pair, first, target);
+    }
+    return rc;
 }
 
 int fdtd_march(fdtd_ctx* c, int64_t n_rows)
@@ -493,22 +620,25 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         if (count != c->p.Nx + 1) return fail(c, FDTD_ESIZE, "a row has Nx+1 = %lld values", (long long)(c->p.Nx + 1));
         if (arg < 0 || arg > c->row || arg < c->row - (c->p.D + 1))
             return fail(c, FDTD_ESTATE, "row %lld is not held (current %lld)", (long long)arg, (long long)c->row);
-        if (dst_on_device) return launch_row_readout(c, arg, (cd*)dst) ? fail(c, FDTD_EDEVICE, "launch failed") : FDTD_OK;
         // stage through the chi scratch (it holds Nx+1 values)
-        rc = launch_row_readout(c, arg, c->b.chi);
+        rc = c->pair ? launch_row_pair(c, arg, dst_on_device ? (cd*)dst : c->b.chi)
+                     : launch_row_readout(c, arg, dst_on_device ? (cd*)dst : c->b.chi);
+        if (dst_on_device) return rc ? fail(c, FDTD_EDEVICE, "launch failed") : FDTD_OK;
         src = c->b.chi;
         break;
     case FDTD_RO_PE:
         esz = 8;
         if (count > c->row + 1) return fail(c, FDTD_ESTATE, "only %lld rows marched", (long long)(c->row + 1));
-        rc = launch_pe_final(c, count, dst_on_device ? (double*)dst : c->b.Pe);
+        rc = c->pair ? launch_pe_pair(c, count, dst_on_device ? (double*)dst : c->b.Pe)
+                     : launch_pe_final(c, count, dst_on_device ? (double*)dst : c->b.Pe);
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.Pe;
         break;
     case FDTD_RO_CHI:
         if (count > c->p.Nx - c->p.D) return fail(c, FDTD_ESIZE, "at most Nx-D = %lld detector separations",
                                                   (long long)(c->p.Nx - c->p.D));
-        rc = launch_chi(c, c->row, count, dst_on_device ? (cd*)dst : c->b.chi);
+        rc = c->pair ? launch_chi_pair(c, c->row, count, dst_on_device ? (cd*)dst : c->b.chi)
+                     : launch_chi(c, c->row, count, dst_on_device ? (cd*)dst : c->b.chi);
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.chi;
         break;
@@ -539,29 +669,34 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.chi;
         break;
-    case FDTD_RO_E:
+    case FDTD_RO_E: {
         if (count > c->p.Nt + 1) return fail(c, FDTD_ESIZE, "E has Nt+1 values");
+        if (arg != 0 && !(c->pair && arg == 1))
+            return fail(c, FDTD_EINVAL, "E: arg selects the photon (0, or 1 for the second of two different photons)");
+        // two different photons: march b carries photon 1's e0, march a photon 2's
+        const cd* Et = c->pair ? (arg == 0 ? c->pair->b.Et : c->b.Et) : c->b.Et;
         if (dst_on_device) {
-            hipError_t e = hipMemcpyAsync(dst, c->b.Et, (size_t)count * 16, hipMemcpyDeviceToDevice, c->stream);
+            hipError_t e = hipMemcpyAsync(dst, Et, (size_t)count * 16, hipMemcpyDeviceToDevice, c->stream);
             return e == hipSuccess ? FDTD_OK : fail(c, FDTD_EDEVICE, "%s", hipGetErrorString(e));
         }
-        src = c->b.Et;
+        src = (void*)Et;
         break;
+    }
     default:
         return fail(c, FDTD_EINVAL, "unknown readout %d", what);
     }
     if (rc) return fail(c, rc, "readout launch failed");
-    int st = 0;
+    int st[2];
     hipError_t e = hipMemcpyAsync(dst, src, (size_t)count * esz, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = status_copy(c, st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "readout copy failed: %s", hipGetErrorString(e));
-    return march_status(c, st);
+    return march_status(c, st[0] | st[1]);
 }
 
 // checkpoint: a header, then the context's workspace (ring, diagonal copy,
 // tables, partial sums) byte for byte
-static int64_t ws_bytes(const fdtd_ctx* c) { return layout(&c->p, c->plan).total; }
+static int64_t ws_bytes(const fdtd_ctx* c) { return ctx_total(&c->p, c->plan); }
 struct CkptHeader {
     char magic[8];
     uint32_t version, header_bytes;
@@ -617,34 +752,40 @@ int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
     if (bytes < sizeof h + (size_t)h.ws_bytes) return fail(c, FDTD_ESIZE, "checkpoint is truncated");
     hipError_t e = hipMemcpyAsync(c->b.ring, (const char*)h_src + sizeof h, (size_t)h.ws_bytes,
                                   hipMemcpyHostToDevice, c->stream);
-    // the delay-equation launch record holds this context's device pointers
-    OdeInst oi;
-    memset(&oi, 0, sizeof oi);
-    oi.g = c->g;
-    oi.pk = c->pk;
-    oi.b = c->b;
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_ode, &oi, sizeof oi, hipMemcpyHostToDevice, c->stream);
+    // the delay-equation launch records hold this context's device pointers
+    OdeInst oi[2];
+    memset(oi, 0, sizeof oi);
+    fdtd_ctx* m[2] = {c, c->pair};
+    for (int i = 0; i < 2 && m[i] && e == hipSuccess; ++i) {
+        oi[i].g = m[i]->g;
+        oi[i].pk = m[i]->pk;
+        oi[i].b = m[i]->b;
+        e = hipMemcpyAsync(m[i]->d_ode, &oi[i], sizeof oi[i], hipMemcpyHostToDevice, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "restore copy failed: %s", hipGetErrorString(e));
-    c->row = h.row;
-    c->strip_row = h.strip_row;
-    c->boundary_ready = (int)h.boundary_ready;
-    c->mu_row = h.mu_row;
+    for (int i = 0; i < 2 && m[i]; ++i) {
+        m[i]->row = h.row;
+        m[i]->strip_row = h.strip_row;
+        m[i]->boundary_ready = (int)h.boundary_ready;
+        m[i]->mu_row = h.mu_row;
+    }
     return FDTD_OK;
 }
 
 int fdtd_sync(fdtd_ctx* c)
 {
     if (!c) return fail(nullptr, FDTD_EINVAL, "ctx is NULL");
-    int st = 0;
-    hipError_t e = hipMemcpyAsync(&st, c->b.status, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    int st[2];
+    hipError_t e = status_copy(c, st);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail(c, FDTD_EDEVICE, "%s", hipGetErrorString(e));
-    return march_status(c, st);
+    return march_status(c, st[0] | st[1]);
 }
 
 int fdtd_destroy(fdtd_ctx* c)
 {
+    if (c) free(c->pair);
     free(c);
     return FDTD_OK;
 }
@@ -736,22 +877,20 @@ extern "C" int fdtd_solve_noalloc(const fdtd_params* p, int64_t n_rows, double* 
     if (rc) return rc;
     // the context lives on this stack frame; its work is enqueued on the
     // caller's stream and needs no host state after the return
-    fdtd_ctx c;
-    rc = ctx_setup(&c, p, SOLO_KNOBS, ws, (size_t)FDTD_NOALLOC_MAX_BYTES, (hipStream_t)hip_stream, why, sizeof why);
+    fdtd_ctx c, c2;                 // c2: the second march of two different photons
+    rc = ctx_setup(&c, &c2, p, SOLO_KNOBS, ws, (size_t)FDTD_NOALLOC_MAX_BYTES, (hipStream_t)hip_stream, why,
+                   sizeof why);
     if (rc) return fail(nullptr, rc, "%s", why);
-    rc = launch_boundary(&c, 0);
+    rc = boundary_enqueue(&c, 0);
     if (rc) return fail(nullptr, rc, "boundary launch failed: %s", hipGetErrorString(hipGetLastError()));
     rc = check_status(&c);
     if (rc) return fail(nullptr, rc, "%s", c.err);
-    c.row = 0;
-    c.strip_row = 0;
-    c.mu_row = c.mupart ? 0 : -1;
-    c.boundary_ready = 1;
+    boundary_done(&c);
     if (n_rows > 0 && (rc = march_to(&c, n_rows)))
         return fail(nullptr, rc, "march launch failed: %s", hipGetErrorString(hipGetLastError()));
-    if (d_pe && (rc = launch_pe_final(&c, n_rows + 1, d_pe)))
+    if (d_pe && (rc = c.pair ? launch_pe_pair(&c, n_rows + 1, d_pe) : launch_pe_final(&c, n_rows + 1, d_pe)))
         return fail(nullptr, rc, "P_e readout launch failed");
-    if (d_row && (rc = launch_row_readout(&c, n_rows, (cd*)d_row)))
+    if (d_row && (rc = c.pair ? launch_row_pair(&c, n_rows, (cd*)d_row) : launch_row_readout(&c, n_rows, (cd*)d_row)))
         return fail(nullptr, rc, "row readout launch failed");
     return FDTD_OK;
 }

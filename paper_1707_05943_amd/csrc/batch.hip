@@ -94,6 +94,10 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
                 al256((int64_t)n * (int64_t)sizeof(ChiJob)) + 256;
     for (int i = 0; i < n; ++i) {
         int rc = ctx_validate(&p[i], kn, why, nwhy);
+        if (!rc && p[i].identical_photons == 0) {
+            snprintf(why, nwhy, "two different photons (identical_photons = 0) are marched one instance at a time");
+            rc = FDTD_EINVAL;
+        }
         if (rc) {
             char tmp[256];
             snprintf(tmp, sizeof tmp, "instance %d: %s", i, why);

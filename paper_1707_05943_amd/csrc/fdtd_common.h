@@ -156,6 +156,14 @@ struct fdtd_ctx {
     cd* Mu;               // mu(t_r) readout staging (Nt+1)
     cd* mupart;           // (Nt+1) x NM_BLOCKS
     int64_t mu_row;
+    // two different photons (Sec. 2 case (c)): this context is march a (phi1 on
+    // the x - t grid, photon 2's e0 and drive), `pair` march b (the photons
+    // exchanged), psi = psi_a + psi_b; xpart holds the row sums of
+    // |psi_a + psi_b|^2 ((Nt+1) x PAIR_CHUNKS) and c0_pair the coefficient
+    // e^{i theta} A/sqrt 2 of chi's free term.  NULL for the other families.
+    fdtd_ctx* pair;
+    double* xpart;
+    cd c0_pair;
     char err[512];
 };
 
@@ -189,6 +197,16 @@ int launch_mu_final(fdtd_ctx* c, int64_t nrows, cd* dst);
 int launch_lambda_final(fdtd_ctx* c, int64_t nrows, double* dst);
 
 constexpr int MAX_HALO = 64;
+
+// two different photons: the exact part of P_e (into march a's Pex), the row
+// sums of |psi_a + psi_b|^2 over rows r0..r1 (PAIR_CHUNKS per row), P_e, a
+// row and chi of the sum
+constexpr int PAIR_CHUNKS = 64;
+int launch_pex_pair(fdtd_ctx* c);
+int launch_pair_rows(fdtd_ctx* c, int64_t r0, int64_t r1);
+int launch_pe_pair(fdtd_ctx* c, int64_t nrows, double* dst);
+int launch_row_pair(fdtd_ctx* c, int64_t rho, cd* dst);
+int launch_chi_pair(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 
 // blocked march: threads per workgroup and columns per thread
 constexpr int BM_THREADS = 512;

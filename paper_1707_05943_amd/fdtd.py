@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
-FDTD_ABI_VERSION = 1
+FDTD_ABI_VERSION = 2
 INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
 RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA, RO_NGEO = 1, 2, 3, 4, 5, 6, 7
 E_SERIES, E_DELAY_ODE = 0, 1
@@ -42,7 +42,10 @@ class FdtdParams(ctypes.Structure):
                 ("Delta", ctypes.c_double), ("omega0", ctypes.c_double), ("Gamma", ctypes.c_double),
                 ("incident", ctypes.c_int32), ("boundary", ctypes.c_int32),
                 ("k", ctypes.c_double), ("alpha", ctypes.c_double), ("x0", ctypes.c_double),
-                ("width", ctypes.c_double), ("phase", ctypes.c_double)]
+                ("width", ctypes.c_double), ("phase", ctypes.c_double),
+                ("identical_photons", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k1", ctypes.c_double), ("k2", ctypes.c_double), ("alpha1", ctypes.c_double),
+                ("alpha2", ctypes.c_double)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -125,7 +128,9 @@ def params(inst) -> FdtdParams:
                       omega0=float(d["omega0"]), Gamma=float(d["Gamma"]), incident=int(d["incident"]),
                       boundary=int(d.get("boundary", 0)), k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
                       x0=float(d.get("x0", 0.0)), width=float(d.get("width", 1.0)),
-                      phase=float(d.get("phase", 0.0)))
+                      phase=float(d.get("phase", 0.0)), identical_photons=int(d.get("identical_photons", 1)),
+                      reserved=0, k1=float(d.get("k1", 0.0)), k2=float(d.get("k2", 0.0)),
+                      alpha1=float(d.get("alpha1", 0.0)), alpha2=float(d.get("alpha2", 0.0)))
 
 
 def workspace_size(inst) -> int:
@@ -252,9 +257,10 @@ class Solver:
         """the geometric measure N_geo of App. D over [0, t_row] (default: the current row)"""
         return float(self._ro(RO_NGEO, self.row if row is None else row, 1, np.float64)[0])
 
-    def E(self) -> np.ndarray:
-        """the boundary table c E(t_r)"""
-        return self._ro(RO_E, 0, self.p.Nt + 1, np.complex128)
+    def E(self, photon: int = 0) -> np.ndarray:
+        """the boundary table c E(t_r); two different photons: photon 0 -> A e^{i theta} e0^(1),
+        photon 1 -> A e^{i theta} e0^(2)"""
+        return self._ro(RO_E, photon, self.p.Nt + 1, np.complex128)
 
     def sync(self):
         self._check(self.lib.fdtd_sync(self.ctx))

@@ -101,8 +101,9 @@ def large_stimulated() -> Instance:
 
 
 def paper_sets() -> dict:
-    """The parameter sets of the paper's validation figures: a two-photon plane
-    wave (identical photons, Eqs. 5-6) in the paper's absolute units, Ny = Nt + 1.
+    """The parameter sets of the paper's figures, in the paper's absolute
+    units, Ny = Nt + 1.  Validation figures: a two-photon plane wave (identical
+    photons, Eqs. 5-6).
     * the error snapshots: nx = 200, Nx = 4000, Ny = 4e4, Delta = 1e-2,
       k = omega0 = pi/2, Gamma = pi/40;
     * |chi|^2 at k0 a = pi/4: nx = 50, Nx = 1e4, Ny = 2.5e4, Delta = 1e-2,
@@ -111,7 +112,10 @@ def paper_sets() -> dict:
       omega0 = pi/2, Gamma = pi/40, with k = omega0 and k = omega0 - Gamma;
     * the strongly non-Markovian cases k0 a = 10.5 pi and 20.5 pi: Nx = 64800,
       Ny = 6e4, Delta = pi/12000, k = omega0 = 100, Gamma = 1 (nx = 2a/Delta =
-      2520 and 4920)."""
+      2520 and 4920).
+    The timing figure (elapsed time against threads): stimulated emission
+    (Eqs. 7-9), Nx = 64800, Ny = 6e4, nx = 960, Delta = 2.618e-4,
+    k = omega0 = 100, Gamma = 5, alpha = 0.5."""
     def plane(name, D, Nx, Ny, Delta, omega0, Gamma, k):
         return Instance(name=name, Nx=int(Nx), D=int(D), Nt=int(Ny) - 1, Delta=float(Delta),
                         omega0=float(omega0), Gamma=float(Gamma), incident=INC_PLANE, k=float(k))
@@ -125,6 +129,8 @@ def paper_sets() -> dict:
         plane("paper_chi_k0a_pi2_det", 200, 10000, 20000, 1e-2, pi / 2, pi / 40, pi / 2 - pi / 40),
         plane("paper_chi_nonmarkov_10.5pi", 2520, 64800, 60000, pi / 12000, 100.0, 1.0, 100.0),
         plane("paper_chi_nonmarkov_20.5pi", 4920, 64800, 60000, pi / 12000, 100.0, 1.0, 100.0),
+        Instance(name="paper_timing_stimulated", Nx=64800, D=960, Nt=59999, Delta=2.618e-4, omega0=100.0,
+                 Gamma=5.0, incident=INC_EXP1, k=100.0, alpha=0.5),
     ):
         out[inst.name] = inst
     return out

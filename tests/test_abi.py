@@ -63,8 +63,34 @@ def test_surrogate_sizes_on_the_host():
 
 
 def test_params_struct_layout_matches_header():
-    # 3 x u32/u32 header + 3 int64 + 3 double + 2 int32 + 5 double
-    assert ctypes.sizeof(fdtd.FdtdParams) == 8 + 24 + 24 + 8 + 40
+    # u32/u32 header + 3 int64 + 3 double + 2 int32 + 5 double + 2 int32 + 4 double
+    assert ctypes.sizeof(fdtd.FdtdParams) == 8 + 24 + 24 + 8 + 40 + 8 + 32
+
+
+def _two(**kw):
+    d = dict(name="two", Nx=1500, D=24, Nt=400, Delta=0.02, omega0=2.0, Gamma=1.0, incident=W.INC_EXP2,
+             identical_photons=0, k1=2.3, k2=1.6, alpha1=0.8, alpha2=1.5, phase=0.4)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kw", [dict(incident=W.INC_GAUSS2, width=1.0, x0=-30.0), dict(alpha2=0.0),
+                                dict(k1=float("inf")), dict(identical_photons=2)])
+def test_two_different_photons_are_validated(kw):
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.workspace_size(_two(**kw))
+    assert e.value.code == -1
+
+
+def test_two_different_photons_take_two_marches():
+    """two marches (psi = psi_a + psi_b) and the row sums of |psi_a + psi_b|^2
+    ((Nt + 1) x 64 doubles)"""
+    two = fdtd.workspace_size(_two())
+    one = fdtd.workspace_size(_two(identical_photons=1, k=2.3, alpha=0.8))
+    assert two == 2 * one + (401 * 64 * 8 + 255) // 256 * 256
+    with pytest.raises(fdtd.FdtdError) as e:                 # batches march one-packet families only
+        fdtd.batch_workspace_size([_two()])
+    assert e.value.code == -1
 
 
 def _bad(**kw):

@@ -145,6 +145,47 @@ def test_march_with_oracle_boundary(name):
     sol.close()
 
 
+TWO_CASES = {
+    # two different exponential photons (Sec. 2 case (c)); a strip of one
+    # workgroup, and a strip wider than a workgroup with the cone
+    "two_D24": W.Instance(name="two_D24", Nx=1500, D=24, Nt=400, Delta=0.02, omega0=2.0, Gamma=1.0,
+                          incident=W.INC_EXP2, identical_photons=0, k1=2.3, k2=1.6, alpha1=0.8, alpha2=1.5,
+                          phase=0.4),
+    "two_D1200": W.Instance(name="two_D1200", Nx=3100, D=1200, Nt=2600, Delta=0.0025, omega0=2.0, Gamma=1.5,
+                            incident=W.INC_EXP2, identical_photons=0, k1=1.1, k2=2.9, alpha1=2.2, alpha2=0.6,
+                            phase=2.0),
+}
+
+
+@pytest.mark.parametrize("name", list(TWO_CASES))
+def test_two_different_photons(name):
+    """psi = psi_a + psi_b from two marches of the library (march a: photon 1
+    on the x - t grid with e0^(2) and photon 2's drive; march b the reverse)
+    against the oracle's march of the full two-product state: rows, chi with
+    its two-product free term, the final ring and P_e with the packets' cross
+    term; then the library's own boundary (both methods) against the oracle's
+    e0^(1), e0^(2)."""
+    inst = TWO_CASES[name]
+    _say(f"[parity] two different photons: {name} D={inst.D} Nx={inst.Nx} Nt={inst.Nt}")
+    E = oracle.E_table(inst)
+    n = inst.Nt + 1
+    sol = fdtd.Solver(inst).set_boundary(E)
+    march_and_compare(inst, sol, E, [inst.Nt // 3, (2 * inst.Nt) // 3], min(64, inst.Nx - inst.D), name)
+    sol.close()
+    c = oracle.two_photon_A(inst) * np.exp(1j * inst.phase)
+    for method in (fdtd.E_SERIES, fdtd.E_DELAY_ODE):
+        i2 = copy.copy(inst)
+        i2.boundary = method
+        sol = fdtd.Solver(i2).set_boundary()
+        for ph, ref in ((0, E[:n]), (1, E[n:])):
+            err = np.max(np.abs(sol.E(ph) / c - ref)) / np.max(np.abs(ref))
+            assert err <= TOL, (method, ph, err)
+        sol.march(inst.Nt)
+        pe_ref = oracle.march(inst, E, want_ring=False)["pe"]
+        assert rel_l2(sol.pe(), pe_ref) <= TOL, (method, rel_l2(sol.pe(), pe_ref))
+        sol.close()
+
+
 E_CASES = {
     "gauss_tiny": _gauss(10, 64, 400, 0.05, 0.5, 3),
     "gauss_wide": _gauss(20, 64, 1500, 0.01, 2.0, 4, k0a=2.0),
