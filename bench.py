@@ -45,9 +45,11 @@ def parse():
     ap.add_argument("--no-nm", action="store_true",
                     help="leave the stimulated-emission march with the measures of App. D out of the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c0", action="store_true", help="leave the D=100, Nx=4000, Nt=4000 instance out")
     ap.add_argument("--cpu-rows", type=int, default=600, help="rows past D in the oracle's sample")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="run only a plain device copy of 4 GiB (3 times), to scale HBM byte counters")
+                    help="run only the library's streaming copy of 21 GB each way (3 times): copy bandwidth and "
+                         "the scale of the HBM byte counters")
     return ap.parse_args()
 
 
@@ -84,17 +86,28 @@ def measured_traffic(workload: str):
 
 
 def calibrate_copy():
-    """A plain copy kernel of known size: FETCH_SIZE / WRITE_SIZE counters of
-    this run, divided by the bytes moved, give the counters' scale."""
+    """The library's streaming copy (fdtd_stream_copy) of 21 GB each way, about
+    the ring's size, three times: its kernel-trace duration gives the copy
+    bandwidth, and its FETCH_SIZE / WRITE_SIZE counters, divided by the bytes
+    moved, give the counters' scale."""
     import torch
-    n = 4 << 30
-    src = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+
+    from paper_1707_05943_amd import fdtd
+    n = 21 * 10**9 // 16 * 16
+    src = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ms = []
     for _ in range(3):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"calibrate_copy_bytes_each_way": n, "copies": 3}), flush=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fdtd.stream_copy(dst, src)
+        b.record(s)
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    print(json.dumps({"calibrate_copy_bytes_each_way": n, "copies": 3, "ms": ms,
+                      "GBps": [2.0 * n / (t * 1e-3) / 1e9 for t in ms]}), flush=True)
 
 
 def cpu_baseline(inst, extra_rows: int) -> dict:
@@ -110,6 +123,7 @@ def cpu_baseline(inst, extra_rows: int) -> dict:
     t2 = time.perf_counter()
     cells = win.Nx * win.Nt
     return {"value": cells / (t2 - t1), "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"march of columns 1..{win.Nx} over rows 1..{win.Nt} of {inst.name} "
                       f"({cells:.3g} cells, {t2 - t1:.1f} s; boundary table {t1 - t0:.1f} s not counted)"}
 
@@ -344,6 +358,116 @@ def run_sweep(n_train: int, n_pts: int, steps: int, tol: float = 1e-3) -> dict:
                          "ms_per_step": (t2 - t1) / steps * 1e3, "batch": 32}}
 
 
+def run_single(inst, steps: int, warmup: int) -> dict:
+    """One instance: a step is the boundary tables, the march of every row,
+    and P_e of every row and chi at 1024 detector separations into device
+    memory.  Events on the march's stream bracket the boundary and the march."""
+    import numpy as np
+    import torch
+
+    from paper_1707_05943_amd import fdtd
+    dev = torch.device("cuda:0")
+    sol = fdtd.Solver(inst, device=str(dev))
+    stream = torch.cuda.current_stream(dev)
+    n_tau = 1024
+    pe_dev = torch.empty(inst.Nt + 1, dtype=torch.float64, device=dev)
+    chi_dev = torch.empty(2 * n_tau, dtype=torch.float64, device=dev)
+    lib = sol.lib
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        sol._check(lib.fdtd_set_boundary(sol.ctx))
+        if ev is not None:
+            ev[1].record(stream)
+        sol._check(lib.fdtd_march(sol.ctx, inst.Nt))
+        if ev is not None:
+            ev[2].record(stream)
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_PE, 0, ctypes.c_void_p(pe_dev.data_ptr()),
+                                    inst.Nt + 1, 1))
+        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_CHI, 0, ctypes.c_void_p(chi_dev.data_ptr()),
+                                    min(n_tau, inst.Nx - inst.D), 1))
+
+    print(f"[bench] {inst.name}: warmup {warmup}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    print(f"[bench] {inst.name}: timing {steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol.sync()                                   # reports a non-finite value in the march
+    ms_step = (t1 - t0) * 1e3 / steps
+    boundary_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+    march_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / steps
+    # the march kernel (k_block): one launch per block of T rows plus one to
+    # start the strip a block ahead; algorithmic bytes per launch are
+    # 32 (Nx + D) T: per cell 16 B written and 16 B of the delay row read,
+    # plus 32 B per strip cell for the mirror reads
+    plan = fdtd.describe(inst)
+    T = plan["T"]
+    launches = (inst.Nt + T - 1) // T + 1
+    bytes_per_launch = 32.0 * (inst.Nx + inst.D) * T
+    avg_launch_s = march_ms * 1e-3 / launches
+    pe = pe_dev.cpu().numpy()
+    sol.close()
+    del sol
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms_step, "march_ms": march_ms, "boundary_ms": boundary_ms, "plan": plan,
+            "launches": launches, "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6,
+            "march_algorithmic_GBps": bytes_per_launch / avg_launch_s / 1e9, "pe_max": float(np.max(pe)),
+            "ring_GB": plan["ring_rows"] * (inst.Nx + 1) * 16 / 1e9}
+
+
+def copy_peak(traffic_bytes: float) -> dict:
+    """The HBM bandwidth a plain copy attains: the library's streaming copy
+    (fdtd_stream_copy) of half the given traffic each way, best of three."""
+    import torch
+
+    from paper_1707_05943_amd import fdtd
+    n = int(traffic_bytes / 2) // 16 * 16
+    src = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    best = float("inf")
+    s = torch.cuda.current_stream()
+    for _ in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        fdtd.stream_copy(dst, src)
+        b.record(s)
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": 2.0 * n / (best * 1e-3) / 1e9,
+            "note": f"library streaming copy of {n / 1e9:.1f} GB each way ({2 * n / 1e9:.1f} GB of traffic), "
+                    f"best of 4: {best:.2f} ms"}
+
+
+def host_cpu() -> dict:
+    """The host the oracle ran on: cores visible to the process and the CPU model (lscpu)."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)",
+                             "CPU max MHz"):
+                info[k.strip()] = v.strip()
+    except Exception:
+        pass
+    return info
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -379,69 +503,48 @@ def main():
         return
 
     inst = W.large_gauss() if args.workload == "large" else W.small_gauss()
-    dev = torch.device("cuda:0")
-    sol = fdtd.Solver(inst, device=str(dev))
-    stream = torch.cuda.current_stream(dev)
-    n_tau = 1024
-    pe_dev = torch.empty(inst.Nt + 1, dtype=torch.float64, device=dev)
-    chi_dev = torch.empty(2 * n_tau, dtype=torch.float64, device=dev)
-    lib = sol.lib
-
-    def step(ev=None):
-        sol._check(lib.fdtd_set_boundary(sol.ctx))
-        if ev is not None:
-            ev[0].record(stream)
-        sol._check(lib.fdtd_march(sol.ctx, inst.Nt))
-        if ev is not None:
-            ev[1].record(stream)
-        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_PE, 0, ctypes.c_void_p(pe_dev.data_ptr()),
-                                    inst.Nt + 1, 1))
-        sol._check(lib.fdtd_readout(sol.ctx, fdtd.RO_CHI, 0, ctypes.c_void_p(chi_dev.data_ptr()),
-                                    n_tau, 1))
-
-    print(f"[bench] {inst.name}: warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    march_ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    one = run_single(inst, args.steps, args.warmup)
+    ms_step = one["ms_per_step"]
     cells = inst.Nx * inst.Nt
     value = cells / (ms_step * 1e-3)
-    # the march kernel (k_block): one launch per block of T rows plus one to
-    # start the strip a block ahead; algorithmic bytes per launch are
-    # 32 (Nx + D) T: per cell 16 B written and 16 B of the delay row read,
-    # plus 32 B per strip cell for the mirror reads
-    plan = fdtd.describe(inst)
-    T = plan["T"]
-    launches = (inst.Nt + T - 1) // T + 1
-    bytes_per_launch = 32.0 * (inst.Nx + inst.D) * T
-    avg_launch_s = march_ms * 1e-3 / launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    pe = pe_dev.cpu().numpy()
+    achieved = one["march_algorithmic_GBps"]
     out = {
         "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": inst.name, "D": inst.D, "Nx": inst.Nx, "Nt": inst.Nt, "Delta": inst.Delta,
-                   "incident": "gaussian two-photon", "ring_GB": (inst.D + 2) * (inst.Nx + 1) * 16 / 1e9,
-                   "march_ms": march_ms, "pe_max": float(np.max(pe))},
+                   "incident": "gaussian two-photon", "ring_GB": one["ring_GB"],
+                   "march_ms": one["march_ms"], "boundary_ms": one["boundary_ms"], "pe_max": one["pe_max"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": "k_block", "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6,
-                     "launches_per_step": launches, "plan": plan},
+                     "kernel": "k_block", "bytes_per_launch": one["bytes_per_launch"],
+                     "avg_launch_us": one["avg_launch_us"], "launches_per_step": one["launches"],
+                     "plan": one["plan"]},
     }
-    sol.close()
-    del sol
+    import torch
     torch.cuda.empty_cache()
+    try:
+        cp = copy_peak(one["ring_GB"] * 1e9)
+        out["roofline"]["copy_peak_GBps"] = cp["GBps"]
+        out["roofline"]["frac_of_copy_peak"] = achieved / cp["GBps"]
+        out["roofline"]["copy_peak_note"] = cp["note"]
+    except Exception as e:                                  # the headline line is printed regardless
+        out["roofline"]["copy_peak_GBps"] = None
+        out["roofline"]["copy_peak_note"] = f"{type(e).__name__}: {e}"
+    if args.workload == "large" and not args.no_c0:
+        print("[bench] D=100, Nx=4000, Nt=4000 instance", file=sys.stderr, flush=True)
+        try:
+            c0 = W.small_gauss()
+            r0 = run_single(c0, max(args.steps, 3), max(args.warmup, 1))
+            out["c0"] = {"workload": c0.name, "ms_per_step": r0["ms_per_step"],
+                         "cell_updates_per_s": c0.Nx * c0.Nt / (r0["ms_per_step"] * 1e-3),
+                         "march_ms": r0["march_ms"], "boundary_ms": r0["boundary_ms"],
+                         "boundary_share": r0["boundary_ms"] / r0["ms_per_step"],
+                         "avg_launch_us": r0["avg_launch_us"], "launches": r0["launches"],
+                         "note": "ring of 11 MB: cache-resident, the march is latency-bound by construction"}
+        except Exception as e:
+            out["c0"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(inst, args.cpu_rows)

@@ -200,6 +200,14 @@ int fdtd_destroy(fdtd_ctx *ctx);
  * NUL-terminated).  Host only; no device work. */
 int fdtd_describe(const fdtd_params *p, char *buf, size_t n);
 
+/* Measurement aid, not part of the method: copy `bytes` (a multiple of 16,
+ * both pointers 16-byte aligned device memory, not overlapping) from d_src
+ * to d_dst with the library's streaming-copy kernel, enqueued on hip_stream.
+ * The HBM bandwidth a plain copy attains is the practical ceiling of the
+ * march's traffic; the benchmark reports the march against it as well as
+ * against the vendor peak.  FDTD_EINVAL on misaligned or NULL arguments. */
+int fdtd_stream_copy(void *d_dst, const void *d_src, size_t bytes, void *hip_stream);
+
 /* Static text for a status code; text of the last failure of ctx (or of the
  * last failed fdtd_init / fdtd_workspace_size / fdtd_solve_noalloc when ctx
  * is NULL). */

@@ -30,7 +30,7 @@ EXPORTS = ("fdtd_workspace_size", "fdtd_init", "fdtd_set_boundary", "fdtd_set_bo
            "fdtd_batch_workspace_size", "fdtd_batch_init", "fdtd_batch_set_boundary", "fdtd_batch_march",
            "fdtd_batch_readout", "fdtd_batch_info", "fdtd_batch_sync", "fdtd_batch_destroy",
            "fdtd_batch_last_error", "fdtd_batch_autotune", "fdtd_batch_set_chi", "fdtd_batch_sample_pe",
-           "fdtd_solve_noalloc")
+           "fdtd_solve_noalloc", "fdtd_stream_copy")
 
 # bytes of the library's own workspace for fdtd_solve_noalloc (FDTD_NOALLOC_MAX_BYTES)
 NOALLOC_MAX_BYTES = 64 << 20
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
     lib.fdtd_batch_set_chi.argtypes = [vp, vp, vp, i64, vp]
     lib.fdtd_batch_sample_pe.argtypes = [vp, i64, vp, vp]
     lib.fdtd_solve_noalloc.argtypes = [P, i64, vp, vp, vp]
+    lib.fdtd_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     _lib = lib
     return lib
 
@@ -172,6 +173,23 @@ def solve_noalloc(inst, n_rows: int, pe_out=None, row_out=None, stream=None) -> 
                                 ctypes.c_void_p(stream.cuda_stream))
     if rc:
         raise FdtdError(rc, lib.fdtd_last_error(None).decode())
+
+
+def stream_copy(dst, src, stream=None) -> None:
+    """fdtd_stream_copy: the library's streaming copy of the device tensor src
+    into dst (same byte size, a multiple of 16), on `stream` (torch's current
+    stream by default)."""
+    import torch
+    lib = load()
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("dst and src differ in size")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib.fdtd_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
+                              ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise FdtdError(rc, "fdtd_stream_copy: misaligned or empty arguments")
 
 
 class Solver:
