@@ -645,6 +645,20 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
     }
 }
 
+// What a segment of strip columns does with the LDS window of the current
+// block (the strip's right end, which the strip's first columns mirror at
+// lags below T):
+enum StripMode {
+    SM_PLAIN = 0,   // no window: every mirror read is older than the block
+    SM_LATE = 1,    // reads the window; column 1's pair psi(D-1, r-1), psi(D, r-1) is written by another wave
+                    // after row r-1's barrier, so its term enters after row r's barrier, as alpha^(j-1)
+                    // times itself in column j (the recurrence is linear)
+    SM_WIN = 2,     // reads the window, every entry of it written before the row's barrier: by a one-wave cone
+                    // (SM_CONE1), or by the same wave (a strip of one wave writes its own window)
+    SM_CONE1 = 3    // a cone of one wave: completes each row, its window entries included, before the row's
+                    // barrier (no carry from another wave is needed)
+};
+
 // The rows of a segment of strip columns (1 <= j <= D): the strip's own
 // workgroups and the cone.  A strip cell's four delay corners lie at
 // x <= -a, so with q = r - j they are Et[r-1-D] (Phi[q] + Phi[q-1]) and
@@ -652,7 +666,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
 // psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (its rows staged
 // through LDS) or, for the strip's first columns, from the LDS window of the
 // current block.  The table here starts one entry before q = S.qa + 1.
-template <bool WIN>
+template <int MODE>
 __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw,
                                            cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
                                            const Seg& S, int64_t ra, int64_t rb, int H1, int T, int cone,
@@ -733,7 +747,10 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     #pragma unroll
     for (int i = 0; i < K; ++i) ap[i] = pw.a[i + 1];
     lp = pw.lp[lane];
-    if constexpr (WIN) lpm = csel(lane > 0, pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1], zero());
+    if constexpr (MODE == SM_LATE) lpm = csel(lane > 0, pw.lp[lane > 0 ? lane - 1 : 0] * pw.a[K - 1], zero());
+    // only cells j <= T - 1 read the window (row r - j inside the block): the
+    // waves past them skip it (a wave-uniform branch)
+    const bool wwave = (MODE == SM_LATE || MODE == SM_WIN) && uni((int)(j0 - K * lane <= T - 1));
     const int64_t R = g.R;
     int64_t sdr = ((ra - j0 + D) % R + R) % R;                  // Md row of diagonal r - j0, row by row
 
@@ -780,22 +797,24 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             // previous row's barrier: its term is added after this row's
             // barrier instead (see below).
             cd m0 = mA[i], m1 = mB[i];
-            if constexpr (WIN) {
-                // window row q - ra = tau - j, column D - j - W.lo (32-bit: j < NT K).
-                // Column 1 is the first cell of lane 0 only (the segment starts
-                // at column 1); column D takes the exact value below.
-                const int jj = (int)j;
-                const int wr = tau - jj;
-                const bool inwin = cell && wr >= 0;
-                const cd* wp = &W.w[0][0] + (inwin ? wr * BM_TMAX + (dwl - jj) : 0);
-                const cd w0 = wp[0], w1 = wp[1];
-                if (i == 0) {
-                    const bool late = (jj == 1);
-                    m0 = csel(inwin, csel(!late, w0, zero()), m0);
-                    m1 = csel(inwin, csel(!late, w1, zero()), m1);
-                } else {
-                    m0 = csel(inwin, w0, m0);
-                    m1 = csel(inwin, w1, m1);
+            if constexpr (MODE == SM_LATE || MODE == SM_WIN) {
+                if (wwave) {
+                    // window row q - ra = tau - j, column D - j - W.lo (32-bit: j < NT K).
+                    // Column 1 is the first cell of lane 0 only (the segment starts
+                    // at column 1); column D takes the exact value below.
+                    const int jj = (int)j;
+                    const int wr = tau - jj;
+                    const bool inwin = cell && wr >= 0;
+                    const cd* wp = &W.w[0][0] + (inwin ? wr * BM_TMAX + (dwl - jj) : 0);
+                    const cd w0 = wp[0], w1 = wp[1];
+                    if (MODE == SM_LATE && i == 0) {
+                        const bool late = (jj == 1);
+                        m0 = csel(inwin, csel(!late, w0, zero()), m0);
+                        m1 = csel(inwin, csel(!late, w1, zero()), m1);
+                    } else {
+                        m0 = csel(inwin, w0, m0);
+                        m1 = csel(inwin, w1, m1);
+                    }
                 }
             }
             if (j == D) m0 = pq * et;                 // psi(0, q)
@@ -810,17 +829,17 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         x = wave_scan(x, pw, lane, nst);
         if (lane == 63) wave_tot[par][wv] = x;
         const cd prevx = dpp_cd<DPP_WAVE_SHR1, 0xF>(x);
-        __syncthreads();
+        if constexpr (MODE != SM_CONE1) __syncthreads();
         stage_put(mstage[par] + soff, Rm, sv, lane);          // stage r+2 (not read if r+2 > rb)
         cd cin = prevx;
-        if (wv > S.w0) cmac(cin, lp, wave_tot[par][wv - 1]);
+        if (MODE != SM_CONE1 && wv > S.w0) cmac(cin, lp, wave_tot[par][wv - 1]);
         if (first) cin = S.exact ? ri.psi0 : zero();
         // the late term of column 1: c4 (psi(D-1, r-1) + psi(D, r-1)) enters
         // column j as alpha^(j-1) times itself (the recurrence is linear), the
         // carry cin (column j0-1) included; past the first wave of the
         // segment its weight is below alpha^(64K)
         cd late = zero(), latep = zero();
-        if constexpr (WIN) {
+        if constexpr (MODE == SM_LATE) {
             if (S.use_win && wv == S.w0 && tau >= 1) {
                 const cd* wl = W.w[tau - 1] + dwl;
                 const cd pd = wl[0];
@@ -841,7 +860,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             const bool act = (j >= act_lo && j <= jmax);
             cd v = u[i];
             cmac(v, ap[i], cin);
-            if constexpr (WIN) {
+            if constexpr (MODE == SM_LATE) {
                 v = v + late;
                 late = late * al;
             }
@@ -858,6 +877,9 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
         if (r + 4 <= rb) fetch(Rm, rinfo[tau + 4].slot);
+        // a one-wave cone's row, window entries included, is complete here:
+        // the strip's next row reads it after this barrier
+        if constexpr (MODE == SM_CONE1) __syncthreads();
     };
 
     for (int64_t r = ra; r <= rb; r += 2) {
@@ -1046,11 +1068,24 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     W.row0 = ra;
 
     cd* wslot = sh.u.f.wslot[threadIdx.x >> 6];
+    // the window's writer completes its rows before their barriers when it is
+    // one wave: a cone of at most 64 K columns, or a strip of one workgroup
+    // whose D columns fit one wave (it writes its own window)
+    const int one_wave_cone = cone && (P.cone_L0 + K - 1) / K <= 64;
+    const int one_wave_strip = is_strip && P.cone_mode == 0 && (D + K - 1) / K <= 64;
     if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage, wslot);
-    else if (is_strip)
-        if (use_win) strip_rows<true>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
-        else strip_rows<false>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
-    else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
+    else if (is_strip) {
+        if (use_win && S.t0 == 0) {
+            if (one_wave_cone || one_wave_strip)
+                strip_rows<SM_WIN>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+            else
+                strip_rows<SM_LATE>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+        } else if (one_wave_cone && S.t0 != 0) {
+            strip_rows<SM_CONE1>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+        } else {
+            strip_rows<SM_PLAIN>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+        }
+    } else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
