@@ -100,6 +100,36 @@ int sur_gemm(int32_t transA, int32_t transB, int32_t M, int32_t N, int32_t K, fl
              int32_t lda, int64_t sA, const float *B, int32_t ldb, int64_t sB, float beta, float *C, int32_t ldc,
              int64_t sC, int32_t batch, void *hip_stream);
 
+/* The sweep's arithmetic around the network (any stream; enqueued).
+ * sur_encode: the network's input for B instances, (B, n, 8) float32 into
+ *   d_x: the incident packet phi(-a - sigma) at sigma_p = 16 w p/(n-1)
+ *   without its normalisation (real, imaginary), then Gamma 2a / 10,
+ *   k0 a / 2 pi, ln w / ln 5, Delta / 0.01, ln(Gamma T) / ln 1000 and p/(n-1);
+ *   d_par holds (w, k0, a, Gamma, Delta, T) per instance (B x 6 doubles), T
+ *   the end of the P_e window.
+ * sur_check: the a-posteriori check of a network's P_e (d_S) for B points of
+ *   n samples, against FP64 solves of the same window and box on grids
+ *   about 2x, 4x and 8x coarser (d_P2, d_P4, d_P8, each B x n), with grid
+ *   steps (h_fine, h_2, h_4, h_8) per point in d_h (B x 4) and d_valid[b] = 0
+ *   where a coarse grid does not exist.  The scheme is second order, so in
+ *   its asymptotic range P_h = P + K h^2: the fine solve differs from P2 by
+ *   about (P4 - P2)(h_2^2 - h_fine^2)/(h_4^2 - h_2^2), and the differences
+ *   of successive coarse solves stand in the ratio
+ *   rho = (h_8^2 - h_4^2)/(h_4^2 - h_2^2).  Per point (L2 norms over the
+ *   samples): dist = |S - P2|/|P2|; est = safety |P4 - P2|/|P2| times that
+ *   factor; q = (|P8 - P4|/|P4 - P2|)/rho, which is 1 in the asymptotic
+ *   range.  The point is in range when |q - 1| <= ratio_tol; it is accepted
+ *   for the coarse solve alone when in range and est <= tol, for the network
+ *   when in range and dist + est <= tol (so every point accepted for the
+ *   network is accepted for the coarse solve).  Writes (dist, est, q) into
+ *   d_out (B x 3 doubles) and the two decisions into d_acc (B x 2 int32).
+ * Both return SUR_EINVAL for null pointers or sizes out of range (n >= 2 for
+ * sur_encode, n >= 1 for sur_check, B >= 0; B = 0 enqueues nothing). */
+int sur_encode(const double *d_par, int32_t B, int32_t n, float *d_x, void *hip_stream);
+int sur_check(const double *d_S, const double *d_P2, const double *d_P4, const double *d_P8, const double *d_h,
+              const int32_t *d_valid, int32_t B, int32_t n, double tol, double safety, double ratio_tol,
+              double *d_out, int32_t *d_acc, void *hip_stream);
+
 int sur_destroy(sur_net *net);
 const char *sur_last_error(const sur_net *net);
 

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
 SOURCES = ["api.hip", "batch.hip", "boundary.hip", "copy.hip", "march_block.hip", "nm.hip", "pair.hip",
-           "readout.hip", "surrogate.hip"]
+           "readout.hip", "surrogate.hip", "sweep.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

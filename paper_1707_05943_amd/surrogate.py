@@ -12,7 +12,7 @@ from . import fdtd
 
 SUR_STATUS = {0: "SUR_OK", -1: "SUR_EINVAL", -2: "SUR_ESIZE", -3: "SUR_ESTATE", -4: "SUR_EDEVICE"}
 EXPORTS = ("sur_sizes", "sur_init", "sur_forward", "sur_backward", "sur_loss", "sur_adam", "sur_reset_moments",
-           "sur_gemm", "sur_destroy", "sur_last_error")
+           "sur_gemm", "sur_destroy", "sur_last_error", "sur_encode", "sur_check")
 
 
 class SurCfg(ctypes.Structure):
@@ -46,6 +46,9 @@ def load():
     lib.sur_reset_moments.argtypes = [vp]
     lib.sur_gemm.argtypes = [i32, i32, i32, i32, i32, f32, vp, i32, i64, vp, i32, i64, f32, vp, i32, i64, i32, vp]
     lib.sur_destroy.argtypes = [vp]
+    lib.sur_encode.argtypes = [vp, i32, i32, vp, vp]
+    lib.sur_check.argtypes = [vp, vp, vp, vp, vp, vp, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp,
+                              vp, vp]
     lib.sur_last_error.argtypes = [vp]
     lib.sur_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -65,6 +68,20 @@ def sizes(c: SurCfg):
     if rc:
         raise SurError(rc, lib.sur_last_error(None).decode())
     return int(n.value), int(b.value)
+
+
+def gemm_flops(c: SurCfg) -> tuple[int, int]:
+    """(forward, backward) flops per sample of the GEMMs sur_forward and
+    sur_backward issue: lift, per layer the DFT to 2*modes rows, the per-mode
+    complex mixing (4 real C x C products), the inverse DFT and the pointwise
+    C x C product, the two projection layers; the backward has the data and
+    the weight gradient of each."""
+    Np, C, M2, P, m = c.n_points, c.width, 2 * c.modes, c.proj, c.modes
+    fwd = 2 * Np * c.c_in * C + c.layers * (2 * M2 * C * Np + 8 * C * C * m + 2 * Np * C * M2 + 2 * Np * C * C) \
+        + 2 * Np * C * P + 2 * Np * P * c.c_out
+    bwd = 4 * Np * P * c.c_out + 4 * Np * C * P \
+        + c.layers * (4 * Np * C * C + 4 * M2 * C * Np + 16 * C * C * m) + 2 * c.c_in * C * Np
+    return fwd, bwd
 
 
 def _p(t):
@@ -89,6 +106,35 @@ def gemm(A, B, C, transA=False, transB=False, alpha=1.0, beta=0.0, M=None, N=Non
     if rc:
         raise SurError(rc, lib.sur_last_error(None).decode())
     return C
+
+
+def encode(par, n, x=None, stream=None):
+    """sur_encode: par (B, 6) float64 device tensor of (w, k0, a, Gamma, Delta, T) -> x (B, n, 8) float32"""
+    import torch
+    lib = load()
+    B = par.shape[0]
+    if x is None:
+        x = torch.empty(B, n, 8, dtype=torch.float32, device=par.device)
+    st = stream if stream is not None else torch.cuda.current_stream(par.device)
+    rc = lib.sur_encode(_p(par), int(B), int(n), _p(x), ctypes.c_void_p(st.cuda_stream))
+    if rc:
+        raise SurError(rc, "sur_encode")
+    return x
+
+
+def check(S, P2, P4, P8, h, valid, tol, safety, ratio_tol, stream=None):
+    """sur_check: (dist, est, q) (B, 3) float64 and accepted (B, 2) bool (network, coarse alone)"""
+    import torch
+    lib = load()
+    B, n = S.shape
+    out = torch.empty(B, 3, dtype=torch.float64, device=S.device)
+    acc = torch.empty(B, 2, dtype=torch.int32, device=S.device)
+    st = stream if stream is not None else torch.cuda.current_stream(S.device)
+    rc = lib.sur_check(_p(S), _p(P2), _p(P4), _p(P8), _p(h), _p(valid), int(B), int(n), float(tol), float(safety),
+                       float(ratio_tol), _p(out), _p(acc), ctypes.c_void_p(st.cuda_stream))
+    if rc:
+        raise SurError(rc, "sur_check")
+    return out, acc.bool()
 
 
 class Net:

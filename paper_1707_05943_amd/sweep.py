@@ -2,9 +2,9 @@
 training, and the surrogate-with-fallback sweep.
 
 Orchestration only: the solves run in the HIP march (fdtd.Batch), the network
-in the HIP surrogate library (surrogate.Net).  Torch device tensors carry the
-data between them; the input encoding and the packing of targets are
-element-wise torch operations on the device.
+and its input encoding in the HIP surrogate library (surrogate.Net,
+surrogate.encode), the a-posteriori check in the library too
+(surrogate.check).  Torch device tensors carry the data between them.
 
 Targets of an instance (n = 1024 samples each):
   * P_e(t_k), t_k = k T_s / (n-1) over T_s = min(Nt Delta, 16 w + 2a + 10/Gamma),
@@ -56,36 +56,55 @@ def chi_plan(inst) -> tuple[int, int]:
     return row, stride
 
 
-def features(insts, device):
-    """(B, n, 8) float32 input encoding on the device"""
+def params_array(insts, device):
+    """(B, 6) float64 device tensor of (w, k0, a, Gamma, Delta, T_s) per instance"""
     import torch
-    n = N_SAMPLES
-    w = torch.tensor([i.width for i in insts], dtype=torch.float64, device=device)[:, None]
-    k0 = torch.tensor([i.k for i in insts], dtype=torch.float64, device=device)[:, None]
-    a = torch.tensor([i.a for i in insts], dtype=torch.float64, device=device)[:, None]
-    G = torch.tensor([i.Gamma for i in insts], dtype=torch.float64, device=device)[:, None]
-    dl = torch.tensor([i.Delta for i in insts], dtype=torch.float64, device=device)[:, None]
-    T = torch.tensor([pe_window(i) for i in insts], dtype=torch.float64, device=device)[:, None]
-    p = torch.arange(n, dtype=torch.float64, device=device)[None, :] / (n - 1)
-    # phi(-a - sigma) with x0 = -a - 8w: x - x0 = 8w - sigma
-    u = 8.0 - 16.0 * p
-    env = torch.exp(-0.25 * u * u)
-    ph = k0 * w * u
-    ones = torch.ones_like(p)
-    x = torch.stack([env * torch.cos(ph), env * torch.sin(ph), (G * 2 * a / 10.0) * ones,
-                     (k0 * a / (2 * math.pi)) * ones, (torch.log(w) / math.log(5.0)) * ones,
-                     (dl / 0.01) * ones, (torch.log(G * T) / math.log(1000.0)) * ones,
-                     p.expand(len(insts), n)], dim=-1)
-    return x.to(torch.float32).contiguous()
+    return torch.tensor([[i.width, i.k, i.a, i.Gamma, i.Delta, pe_window(i)] for i in insts], dtype=torch.float64,
+                        device=device)
+
+
+def features(insts, device):
+    """(B, n, 8) float32 input encoding on the device (the library's sur_encode)"""
+    return S.encode(params_array(insts, device), N_SAMPLES)
+
+
+def params_from_arrays(d, lo, hi, device):
+    """params_array of points lo..hi-1 of a workloads.sweep_draw_arrays draw"""
+    import torch
+    sl = slice(lo, hi)
+    w, a, dl = d["width"][sl], d["a"][sl], d["Delta"][sl]
+    ts = np.minimum(d["Nt"][sl] * dl, 16.0 * w + 2.0 * a + 10.0)
+    par = np.stack([w, d["k0"][sl], a, np.ones_like(w), dl, ts], axis=1)
+    return torch.from_numpy(np.ascontiguousarray(par)).to(device)
+
+
+def box(inst):
+    """the instance with its box cut to the largest multiple of the round
+    trip 2a inside it (Nx = floor(Nx / D) D): the box's right edge is then a
+    node of every grid that keeps a exactly, so the P_e of a coarser grid
+    (exact part plus the box integral) is the same physical quantity.  The
+    march of columns 0..Nx does not depend on columns beyond Nx."""
+    Nx = (inst.Nx // inst.D) * inst.D
+    return inst if Nx == inst.Nx else W.Instance(**{**inst.as_dict(), "Nx": Nx})
+
+
+def draw(n: int, seed: int):
+    """workloads.sweep_draw with each box cut by box()"""
+    return [box(i) for i in W.sweep_draw(n, seed)]
 
 
 def coarse(inst, factor: int):
     """the same physical problem on a grid about `factor` times coarser: D_c
-    even and a kept exactly (so Delta_c = 2a / D_c), the box and the window
-    covered"""
+    even and a kept exactly (so Delta_c = 2a / D_c), the same box (the
+    instance's box must be a multiple of 2a, see box()) and the time window
+    covered; None where no such grid exists"""
+    if inst.Nx % inst.D:
+        raise ValueError(f"{inst.name}: the box (Nx = {inst.Nx}) is not a multiple of D = {inst.D}")
     D_c = max(2, 2 * int(round(inst.D / (2.0 * factor))))
+    if D_c >= inst.D:
+        return None
     d_c = 2.0 * inst.a / D_c
-    Nx_c = max(D_c + 1, int(math.ceil(inst.Nx * inst.Delta / d_c)))
+    Nx_c = (inst.Nx // inst.D) * D_c
     Nt_c = int(math.ceil(inst.Nt * inst.Delta / d_c - 1e-9))
     c = W.Instance(**{**inst.as_dict(), "D": D_c, "Delta": d_c, "Nx": Nx_c, "Nt": Nt_c,
                       "name": f"{inst.name}_c{factor}"})
@@ -220,136 +239,91 @@ def rel_err(a, b):
     return torch.linalg.norm(a - b, dim=1) / torch.clamp(torch.linalg.norm(b, dim=1), min=1e-300)
 
 
-def sweep(insts, net, solver: Solver, tol=1e-3, accept=None, factor=4, chunk=512, log=None):
-    """Surrogate with a-posteriori check and FP64 fallback, for P_e.
-
-    For each point: the surrogate's P_e; a coarse FP64 solve (grid `factor`
-    times coarser, same physical window); the surrogate is accepted where its
-    relative L2 distance to the coarse solve is at most `accept` (default
-    tol / 2), otherwise the point is re-solved on its own grid.  Returns the
-    P_e of every point, the accepted mask and timings."""
+def coarse_pe(insts, solver: Solver, factor: int, chunk=512):
+    """P_e of each point on its `factor`-coarser grid, sampled on the point's
+    own window; (pe (B, n), valid (B,) bool, grid steps (B,) as a list).
+    Batches hold chunk * factor^2 points (about the cells and the memory of
+    `chunk` points on their own grids)."""
     import torch
-    accept = tol / 2 if accept is None else accept
+    dev = solver.device
+    cs = [coarse(i, factor) for i in insts]
+    have = [i for i, c in enumerate(cs) if c is not None]
+    pe = torch.zeros(len(insts), N_SAMPLES, dtype=torch.float64, device=dev)
+    step = min(chunk * factor * factor, 16384)
+    for s in range(0, len(have), step):
+        ids = have[s:s + step]
+        p, _, _ = solver.solve([cs[i] for i in ids], with_chi=False, t_end=[pe_window(insts[i]) for i in ids])
+        pe[torch.tensor(ids, device=dev)] = p
+    valid = torch.zeros(len(insts), dtype=torch.bool, device=dev)
+    if have:
+        valid[torch.tensor(have, device=dev)] = True
+    return pe, valid, [c.Delta if c is not None else float("nan") for c in cs]
+
+
+SAFETY = 2.0        # the check's factor on the leading-order estimate of the coarse solve's error
+RATIO_TOL = 0.25    # the check's band on the observed/expected ratio of successive coarse differences
+
+
+def sweep(insts, net, solver: Solver, tol=1e-3, safety=SAFETY, ratio_tol=RATIO_TOL, chunk=512, log=None):
+    """Surrogate with an a-posteriori check and FP64 fallback, for P_e, next
+    to the same check without the network.  Points must have boxes that are
+    multiples of 2a (box()).
+
+    Each point: the network's P_e (S); FP64 solves of the same window and box
+    on grids about 2x, 4x and 8x coarser (P2, P4, P8).  In the scheme's
+    asymptotic range (checked: successive differences in the ratio the grid
+    steps give, within ratio_tol) the fine solve differs from P2 by about
+    (P4 - P2)(h2^2 - h^2)/(h4^2 - h2^2); with that estimate (times `safety`)
+    the network's answer is within tol of the fine solve when |S - P2|/|P2| +
+    est <= tol, and P2 itself is when est <= tol; points that fail are solved
+    on their own grid.  Whenever the first holds, so does the second: under a
+    check that bounds the true error, the network path accepts a subset of
+    what the coarse solve alone does, at the check's cost plus inference.
+    Returns (P_e of the network path, P_e of the coarse path, accepted (B, 2)
+    bool: network, coarse; (dist, est, q) (B, 3); timings and P2)."""
+    import torch
     dev = solver.device
     t0 = time.perf_counter()
     x = torch.cat([features(insts[s:s + chunk], dev) for s in range(0, len(insts), chunk)])
     s_pe = predict_pe(net, x)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # coarse solves of the points that have a valid coarse grid (the others fall back)
-    cs = [coarse(i, factor) for i in insts]
-    have = [i for i, c in enumerate(cs) if c is not None]
-    ok = torch.zeros(len(insts), dtype=torch.bool, device=dev)
-    for s in range(0, len(have), chunk):
-        ids = have[s:s + chunk]
-        pe, _, _ = solver.solve([cs[i] for i in ids], with_chi=False, t_end=[pe_window(insts[i]) for i in ids])
-        idx = torch.tensor(ids, device=dev)
-        ok[idx] = rel_err(s_pe[idx], pe) <= accept
-    t2 = time.perf_counter()
-    out = s_pe.clone()
-    fb = [i for i, a in enumerate(ok.tolist()) if not a]
-    for s in range(0, len(fb), chunk):
-        ids = fb[s:s + chunk]
-        pe, _, _ = solver.solve([insts[i] for i in ids], with_chi=False)
-        out[torch.tensor(ids, device=dev)] = pe
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    if log:
-        log(f"[sweep] {len(insts)} points: surrogate {t1 - t0:.2f} s, check {t2 - t1:.2f} s, "
-            f"fallback {len(fb)} points {t3 - t2:.2f} s")
-    return out, ok, {"surrogate_s": t1 - t0, "check_s": t2 - t1, "fallback_s": t3 - t2, "total_s": t3 - t0,
-                     "fallback": len(fb), "points": len(insts)}
-
-
-# ---------------------------------------------------------------------------
-# Corrected sweep: a network predicts the difference between the fine solve's
-# P_e and that of a 4x coarser FP64 solve; the a-posteriori check compares the
-# prediction with the Richardson estimate of the same difference from a
-# second, 8x coarser solve (the scheme is second order:
-# P_h = P + K h^2, so P_fine - P_4 = (P_8 - P_4)(Delta^2 - h_4^2)/(h_8^2 - h_4^2)).
-# ---------------------------------------------------------------------------
-CORR_SCALE = 100.0          # default scale of the difference seen by the network (set from the data)
-
-
-def coarse_pe(insts, solver: Solver, factor: int, chunk=512):
-    """P_e of each point on its `factor`-coarser grid, sampled on the point's
-    own window; (pe (B, n), valid (B,) bool, grid steps (B,))"""
-    import torch
-    dev = solver.device
-    cs = [coarse(i, factor) for i in insts]
-    have = [i for i, c in enumerate(cs) if c is not None]
-    pe = torch.zeros(len(insts), N_SAMPLES, dtype=torch.float64, device=dev)
-    for s in range(0, len(have), chunk):
-        ids = have[s:s + chunk]
-        p, _, _ = solver.solve([cs[i] for i in ids], with_chi=False, t_end=[pe_window(insts[i]) for i in ids])
-        pe[torch.tensor(ids, device=dev)] = p
-    valid = torch.zeros(len(insts), dtype=torch.bool, device=dev)
-    if have:
-        valid[torch.tensor(have, device=dev)] = True
-    h = torch.tensor([c.Delta if c is not None else float("nan") for c in cs], dtype=torch.float64, device=dev)
-    return pe, valid, h
-
-
-def corrector_inputs(insts, c4, device):
-    """the surrogate's encoding plus the coarse solve's P_e as a ninth channel"""
-    import torch
-    return torch.cat([features(insts, device), c4.to(torch.float32)[:, :, None]], dim=2).contiguous()
-
-
-def make_corrector_dataset(insts, solver: Solver, chunk=512, log=None, fine=None):
-    """inputs and targets (P_fine - P_4) x CORR_SCALE of the points whose
-    coarse grid is valid (`fine`: the points' fine P_e samples, if at hand)"""
-    import torch
-    if fine is None:
-        fine = torch.cat([solver.solve(insts[s:s + chunk], with_chi=False)[0] for s in range(0, len(insts), chunk)])
-    fine = fine.to(torch.float64)
-    c4, v4, _ = coarse_pe(insts, solver, 4, chunk)
-    keep = [i for i, v in enumerate(v4.tolist()) if v]
-    idx = torch.tensor(keep, device=solver.device)
-    x = corrector_inputs([insts[i] for i in keep], c4[idx], solver.device)
-    d = fine[idx] - c4[idx]
-    scale = 1.0 / max(float(torch.sqrt(torch.mean(d * d))), 1e-300)     # unit RMS targets
-    t = (d * scale).to(torch.float32)[:, :, None].contiguous()
-    m = torch.ones_like(t)
-    if log:
-        log(f"[sweep] corrector data: {len(keep)} of {len(insts)} points have a coarse grid, "
-            f"difference RMS {1.0 / scale:.3e}")
-    return x, t, m, scale
-
-
-def sweep_corrected(insts, net, solver: Solver, tol=1e-3, accept=None, chunk=512, log=None):
-    """P_e of every point: coarse solve + network correction where the check
-    passes (the two estimates of the correction agree within tol/4 relative),
-    the fine FP64 solve elsewhere.  Returns (P_e, accepted, info,
-    Richardson-only estimate)."""
-    import torch
-    accept = tol / 4 if accept is None else accept
-    dev = solver.device
-    t0 = time.perf_counter()
-    c4, v4, h4 = coarse_pe(insts, solver, 4, chunk)
-    c8, v8, h8 = coarse_pe(insts, solver, 8, chunk)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    x = corrector_inputs(insts, c4, dev)
-    d_nn = predict_pe(net, x) / getattr(net, "corr_scale", CORR_SCALE)
+    p2, v2, h2 = coarse_pe(insts, solver, 2, chunk)
+    p4, v4, h4 = coarse_pe(insts, solver, 4, chunk)
+    p8, v8, h8 = coarse_pe(insts, solver, 8, chunk)
+    h = torch.tensor([[i.Delta, a, b, c] for i, a, b, c in zip(insts, h2, h4, h8)], dtype=torch.float64, device=dev)
+    h = torch.nan_to_num(h, nan=1.0)
+    de, acc = S.check(s_pe, p2, p4, p8, h, (v2 & v4 & v8).to(torch.int32), tol, safety, ratio_tol)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    hf = torch.tensor([i.Delta for i in insts], dtype=torch.float64, device=dev)
-    w = ((hf ** 2 - h4 ** 2) / (h8 ** 2 - h4 ** 2))[:, None]
-    d_r = (c8 - c4) * w
-    scale = torch.clamp(torch.linalg.norm(c4, dim=1), min=1e-300)
-    ok = v4 & v8 & (torch.linalg.norm(d_nn - d_r, dim=1) / scale <= accept)
-    out = c4 + d_nn
-    rich = torch.where((v4 & v8)[:, None], c4 + d_r, torch.full_like(c4, float("nan")))
-    fb = [i for i, a in enumerate(ok.tolist()) if not a]
-    for s in range(0, len(fb), chunk):
-        ids = fb[s:s + chunk]
-        pe, _, _ = solver.solve([insts[i] for i in ids], with_chi=False)
-        out[torch.tensor(ids, device=dev)] = pe
-    torch.cuda.synchronize()
+    # fallback: the coarse path rejects a subset of what the network path rejects
+    rej_c = [i for i, a in enumerate(acc[:, 1].tolist()) if not a]
+    rej_s_only = [i for i, (a, b) in enumerate(acc.tolist()) if b and not a]
+    fine = {}
+    t_parts = []
+    for group in (rej_c, rej_s_only):
+        tg = time.perf_counter()
+        for s in range(0, len(group), chunk):
+            ids = group[s:s + chunk]
+            pe, _, _ = solver.solve([insts[i] for i in ids], with_chi=False)
+            for k, i in enumerate(ids):
+                fine[i] = pe[k]
+        torch.cuda.synchronize()
+        t_parts.append(time.perf_counter() - tg)
+    out_s = s_pe.clone()
+    out_c = p2.clone()
+    in_c = set(rej_c)
+    for i, v in fine.items():
+        out_s[i] = v
+        if i in in_c:
+            out_c[i] = v
     t3 = time.perf_counter()
+    info = {"points": len(insts), "inference_s": t1 - t0, "check_s": t2 - t1,
+            "fallback_coarse_path_s": t_parts[0], "fallback_network_path_s": t_parts[0] + t_parts[1],
+            "accepted_network": int(acc[:, 0].sum()), "accepted_coarse": int(acc[:, 1].sum()),
+            "network_path_s": (t1 - t0) + (t2 - t1) + t_parts[0] + t_parts[1],
+            "coarse_path_s": (t2 - t1) + t_parts[0], "assemble_s": t3 - t2 - sum(t_parts), "p2": p2}
     if log:
-        log(f"[sweep] corrected, {len(insts)} points: coarse solves {t1 - t0:.2f} s, network {t2 - t1:.2f} s, "
-            f"fallback {len(fb)} points {t3 - t2:.2f} s")
-    return out, ok, {"coarse_s": t1 - t0, "network_s": t2 - t1, "fallback_s": t3 - t2, "total_s": t3 - t0,
-                     "fallback": len(fb), "points": len(insts)}, rich
+        log(f"[sweep] {len(insts)} points: inference {t1 - t0:.2f} s, check {t2 - t1:.2f} s; accepted network "
+            f"{info['accepted_network']}, coarse alone {info['accepted_coarse']}")
+    return out_s, out_c, acc, de, info

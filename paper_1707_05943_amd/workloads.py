@@ -186,3 +186,33 @@ def sweep_draw(n: int, seed: int) -> list[Instance]:
                             x0=-a - 8.0 * width, width=width, phase=theta, seed=seed * 100003 + i,
                             boundary=1))
     return out
+
+
+def sweep_draw_arrays(n: int, seed: int) -> dict:
+    """The distribution of sweep_draw as arrays, for draws too large to hold
+    as Instance objects (a million points): Gamma = 1; each column is drawn
+    as a whole (so the points differ from sweep_draw's for the same seed).
+    Keys: two_a, k0a, width, Delta, theta and the derived D, a, Nx, Nt, k0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    two_a = rng.uniform(0.1, 10.0, n)
+    k0a = rng.uniform(0.0, 2.0 * math.pi, n)
+    width = np.exp(rng.uniform(math.log(0.2), math.log(5.0), n))
+    Delta = rng.choice(np.array([0.01, 0.005, 0.002]), n)
+    theta = 2.0 * math.pi * rng.random(n)
+    D = 2 * np.maximum(1, np.round(0.5 * two_a / Delta).astype(np.int64))
+    a = 0.5 * D * Delta
+    need = np.maximum(2 * D, np.ceil((16.0 * width + 2.0 * a + 10.0) / (4.0 * Delta)).astype(np.int64))
+    Nx = np.clip(1 << np.ceil(np.log2(np.maximum(need, 1))).astype(np.int64), 1024, 16384)
+    Nx = np.where(Nx < need, 2 * Nx, Nx).clip(1024, 16384)       # guard the float log2 at exact powers
+    return {"two_a": two_a, "k0a": k0a, "width": width, "Delta": Delta, "theta": theta, "D": D, "a": a,
+            "Nx": Nx, "Nt": 4 * Nx, "k0": k0a / a, "seed": seed}
+
+
+def sweep_point(d: dict, i: int) -> Instance:
+    """point i of a sweep_draw_arrays draw as an Instance"""
+    a, w = float(d["a"][i]), float(d["width"][i])
+    k0 = float(d["k0"][i])
+    return Instance(name=f"sweepA{d['seed']}_{i}", Nx=int(d["Nx"][i]), D=int(d["D"][i]), Nt=int(d["Nt"][i]),
+                    Delta=float(d["Delta"][i]), omega0=k0, Gamma=1.0, incident=INC_GAUSS2, k=k0,
+                    x0=-a - 8.0 * w, width=w, phase=float(d["theta"][i]), seed=int(d["seed"]) * 1000003 + i,
+                    boundary=1)
