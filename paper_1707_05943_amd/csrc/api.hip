@@ -176,30 +176,68 @@ static void gl_rule(int n, double* x, double* w)
     }
 }
 
-// collocation weights of one step of the delay equation (OdeTab)
-static void ode_table(const Geom& g, OdeTab* T)
+// What the collocation weights of one step of the delay equation (OdeTab)
+// need that does not depend on the instance, in units of Delta: the nodes
+// s_i = tau_i / Delta (Gauss-Legendre on (0, 1), then s_P = 1), and for the
+// integral over (0, s_i) of row i its NQ Gauss-Legendre nodes u, their
+// weights and the Lagrange basis of the nodes s_0..s_{P-1} at them.
+constexpr int ODE_NQ = 48;
+struct OdeUnit {
+    double s[ODE_P + 1];
+    double u[ODE_P + 1][ODE_NQ];
+    double wq[ODE_P + 1][ODE_NQ];
+    double l[ODE_P + 1][ODE_NQ][ODE_P];
+};
+
+static OdeUnit make_ode_unit()
 {
-    double x[ODE_P], w[ODE_P];
+    OdeUnit U;
+    double x[ODE_P], w[ODE_P], xq[ODE_NQ], wq[ODE_NQ];
     gl_rule(ODE_P, x, w);
-    for (int i = 0; i < ODE_P; ++i) T->tau[i] = 0.5 * g.Delta * (1.0 + x[i]);
-    T->tau[ODE_P] = g.Delta;
-    enum { NQ = 48 };
-    double xq[NQ], wq[NQ];
-    gl_rule(NQ, xq, wq);
+    gl_rule(ODE_NQ, xq, wq);
+    for (int i = 0; i < ODE_P; ++i) U.s[i] = 0.5 * (1.0 + x[i]);
+    U.s[ODE_P] = 1.0;
     for (int i = 0; i <= ODE_P; ++i) {
-        const double ti = T->tau[i];
-        T->ew[i] = cexp_(-(g.W * ti));
-        for (int j = 0; j < ODE_P; ++j) {
-            cd acc = mk(0.0, 0.0);
-            for (int q = 0; q < NQ; ++q) {
-                const double u = 0.5 * ti * (1.0 + xq[q]);
+        for (int q = 0; q < ODE_NQ; ++q) {
+            const double u = 0.5 * U.s[i] * (1.0 + xq[q]);
+            U.u[i][q] = u;
+            U.wq[i][q] = 0.5 * U.s[i] * wq[q];
+            for (int j = 0; j < ODE_P; ++j) {
                 double lj = 1.0;
                 for (int k = 0; k < ODE_P; ++k)
-                    if (k != j) lj *= (u - T->tau[k]) / (T->tau[j] - T->tau[k]);
-                acc += (0.5 * ti * wq[q] * lj) * cexp_(-(g.W * (ti - u)));
+                    if (k != j) lj *= (u - U.s[k]) / (U.s[j] - U.s[k]);
+                U.l[i][q][j] = lj;
             }
-            T->M[i][j] = acc;
         }
+    }
+    return U;
+}
+
+static const OdeUnit& ode_unit()
+{
+    static const OdeUnit U = make_ode_unit();
+    return U;
+}
+
+// collocation weights of one step of the delay equation (OdeTab): tau_i =
+// Delta s_i, ew_i = e^{-W tau_i} and M_ij = int_0^{tau_i} l_j(u) e^{-W (tau_i
+// - u)} du by the quadrature of OdeUnit
+static void ode_table(const Geom& g, OdeTab* T)
+{
+    const OdeUnit& U = ode_unit();
+    const double h = g.Delta;
+    for (int i = 0; i <= ODE_P; ++i) {
+        const double ti = h * U.s[i];
+        T->tau[i] = ti;
+        T->ew[i] = cexp_(-(g.W * ti));
+        cd acc[ODE_P];
+        for (int j = 0; j < ODE_P; ++j) acc[j] = mk(0.0, 0.0);
+        for (int q = 0; q < ODE_NQ; ++q) {
+            const cd e = cexp_(-(g.W * (h * (U.s[i] - U.u[i][q]))));
+            const double wt = h * U.wq[i][q];
+            for (int j = 0; j < ODE_P; ++j) acc[j] += (wt * U.l[i][q][j]) * e;
+        }
+        for (int j = 0; j < ODE_P; ++j) T->M[i][j] = acc[j];
     }
 }
 
@@ -240,9 +278,11 @@ static double two_photon_A(const fdtd_params* p)
 // One march in *c over the workspace at `base` (layout L): photon 0 for the
 // one-packet families; for two different photons 2 (march a: photon 2's e0
 // and drive) or 1 (march b: photon 1's).  Enqueues the clearing of the ring
-// and the copies of the boundary's step weights and waits for them.
+// and the copies of the boundary's step weights and waits for them; with
+// `defer` it does neither and hands the step weights and the launch record
+// to the caller (see CtxDefer).
 static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const Layout& L, char* base, int photon,
-                       hipStream_t stream, char* why, size_t nwhy)
+                       hipStream_t stream, char* why, size_t nwhy, const CtxDefer* defer)
 {
     const int64_t nblk = P.nwg;
     int rc = FDTD_OK;
@@ -300,10 +340,15 @@ static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const L
     c->row = -1;
     c->strip_row = -1;
     c->boundary_ready = 0;
-    rc = launch_clear(c);
-    if (rc) {
-        snprintf(why, nwhy, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError()));
-        return rc;
+    if (defer) {
+        b.ode = defer->d_tab;
+        c->d_ode = nullptr;
+    } else {
+        rc = launch_clear(c);
+        if (rc) {
+            snprintf(why, nwhy, "clearing the ring failed: %s", hipGetErrorString(hipGetLastError()));
+            return rc;
+        }
     }
     // the delay-equation boundary's step weights and launch record
     OdeTab tab;
@@ -313,6 +358,12 @@ static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const L
     oi.g = g;
     oi.pk = pk;
     oi.b = b;
+    oi.nblk = nblk;
+    if (defer) {
+        *defer->h_tab = tab;
+        *defer->h_inst = oi;
+        return FDTD_OK;
+    }
     hipError_t e = hipMemcpyAsync(b.ode, &tab, sizeof tab, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipMemcpyAsync(c->d_ode, &oi, sizeof oi, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -327,7 +378,7 @@ static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const L
 // *pair, march b) for parameters p over the caller's workspace.  Allocates
 // nothing.
 static int ctx_setup(fdtd_ctx* c, fdtd_ctx* pair, const fdtd_params* p, const PlanKnobs& kn, void* d_workspace,
-                     size_t bytes, hipStream_t stream, char* why, size_t nwhy)
+                     size_t bytes, hipStream_t stream, char* why, size_t nwhy, const CtxDefer* defer = nullptr)
 {
     int rc = ctx_validate(p, kn, why, nwhy);
     if (rc) return rc;
@@ -342,10 +393,11 @@ static int ctx_setup(fdtd_ctx* c, fdtd_ctx* pair, const fdtd_params* p, const Pl
     if (((uintptr_t)d_workspace) & 255) { snprintf(why, nwhy, "workspace must be 256-byte aligned"); return FDTD_EINVAL; }
     const int two = two_photons(p);
     if (two && !pair) { snprintf(why, nwhy, "two different photons need the second march's context"); return FDTD_EINVAL; }
+    if (two && defer) { snprintf(why, nwhy, "two different photons are set up one instance at a time"); return FDTD_EINVAL; }
     char* base = (char*)d_workspace;
-    rc = march_setup(c, p, P, L, base, two ? 2 : 0, stream, why, nwhy);
+    rc = march_setup(c, p, P, L, base, two ? 2 : 0, stream, why, nwhy, defer);
     if (rc || !two) return rc;
-    rc = march_setup(pair, p, P, L, base + L.total, 1, stream, why, nwhy);
+    rc = march_setup(pair, p, P, L, base + L.total, 1, stream, why, nwhy, nullptr);
     if (rc) return rc;
     c->pair = pair;
     c->xpart = (double*)(base + 2 * L.total);
@@ -354,7 +406,7 @@ static int ctx_setup(fdtd_ctx* c, fdtd_ctx* pair, const fdtd_params* p, const Pl
 }
 
 int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, size_t bytes, hipStream_t stream,
-               fdtd_ctx** out, char* why, size_t nwhy)
+               fdtd_ctx** out, char* why, size_t nwhy, const CtxDefer* defer)
 {
     int rc = ctx_validate(p, kn, why, nwhy);
     if (rc) return rc;
@@ -368,7 +420,7 @@ int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_workspace, siz
         snprintf(why, nwhy, "out of host memory");
         return FDTD_EDEVICE;
     }
-    rc = ctx_setup(c, pair, p, kn, d_workspace, bytes, stream, why, nwhy);
+    rc = ctx_setup(c, pair, p, kn, d_workspace, bytes, stream, why, nwhy, defer);
     if (rc) {
         free(pair);
         free(c);
@@ -760,6 +812,7 @@ int fdtd_restore(fdtd_ctx* c, const void* h_src, size_t bytes)
         oi[i].g = m[i]->g;
         oi[i].pk = m[i]->pk;
         oi[i].b = m[i]->b;
+        oi[i].nblk = m[i]->nblk;
         e = hipMemcpyAsync(m[i]->d_ode, &oi[i], sizeof oi[i], hipMemcpyHostToDevice, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

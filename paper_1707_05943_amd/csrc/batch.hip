@@ -23,6 +23,8 @@ struct fdtd_batch {
     BInst* d_tab = nullptr;          // in the workspace
     OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
     int n_ode = 0;
+    OdeTab* d_otab = nullptr;        // every instance's delay-equation step weights
+    int* d_stat = nullptr;           // every instance's status word, gathered for one copy
     ChiJob* d_jobs = nullptr;        // chi snapshots, sorted by the launch after which they are taken
     int* d_status = nullptr;         // the batch's status word (non-finite values in any instance's march)
     std::vector<int> job_begin;      // per launch k: first job, and one past the last (job_begin[k+1])
@@ -91,7 +93,8 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
 {
     const PlanKnobs kn = knobs_of(o);
     int64_t t = al256((int64_t)n * (int64_t)sizeof(BInst)) + al256((int64_t)n * (int64_t)sizeof(OdeInst)) +
-                al256((int64_t)n * (int64_t)sizeof(ChiJob)) + 256;
+                al256((int64_t)n * (int64_t)sizeof(ChiJob)) + 256 + al256((int64_t)n * (int64_t)sizeof(OdeTab)) +
+                al256((int64_t)n * (int64_t)sizeof(int));
     for (int i = 0; i < n; ++i) {
         int rc = ctx_validate(&p[i], kn, why, nwhy);
         if (!rc && p[i].identical_photons == 0) {
@@ -194,10 +197,18 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
     off += al256((int64_t)n * (int64_t)sizeof(ChiJob));
     b->d_status = (int*)(base + off);
     off += 256;
+    b->d_otab = (OdeTab*)(base + off);
+    off += al256((int64_t)n * (int64_t)sizeof(OdeTab));
+    b->d_stat = (int*)(base + off);
+    off += al256((int64_t)n * (int64_t)sizeof(int));
+    // contexts set up on the host only; the device side follows in bulk
+    std::vector<OdeTab> otab(n);
+    std::vector<OdeInst> oinst(n);
     for (int i = 0; i < n; ++i) {
         const int64_t sz = ctx_bytes(&p[i], kn);
         fdtd_ctx* c = nullptr;
-        rc = ctx_create(&p[i], kn, base + off, (size_t)sz, b->stream, &c, why, sizeof why);
+        const CtxDefer df = {b->d_otab + i, &otab[i], &oinst[i]};
+        rc = ctx_create(&p[i], kn, base + off, (size_t)sz, b->stream, &c, why, sizeof why, &df);
         if (rc) {
             destroy(b);
             return bfail(nullptr, rc, "instance %d: %s", i, why);
@@ -244,15 +255,23 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
         }
         b->nb[k] = (int)(((w + 7) / 8) * 8);
     }
+    // delay-equation boundaries: one workgroup each in one launch, longest first
+    std::vector<OdeInst> ode;
+    for (int q2 = 0; q2 < n; ++q2) {
+        const int i = b->order[q2];
+        if (b->c[i]->p.boundary != FDTD_E_DELAY_ODE) continue;
+        b->c[i]->d_ode = b->d_ode + ode.size();
+        ode.push_back(oinst[i]);
+    }
+    b->n_ode = (int)ode.size();
     hipError_t e = hipMemcpyAsync(b->d_tab, b->h_tab.data(), (size_t)n * sizeof(BInst), hipMemcpyHostToDevice,
                                   b->stream);
-    // delay-equation boundaries: one workgroup each in one launch, longest first
-    for (int q2 = 0; q2 < n && e == hipSuccess; ++q2) {
-        fdtd_ctx* c = b->c[b->order[q2]];
-        if (c->p.boundary != FDTD_E_DELAY_ODE) continue;
-        e = hipMemcpyAsync(b->d_ode + b->n_ode, c->d_ode, sizeof(OdeInst), hipMemcpyDeviceToDevice, b->stream);
-        ++b->n_ode;
-    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_otab, otab.data(), (size_t)n * sizeof(OdeTab), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess && b->n_ode)
+        e = hipMemcpyAsync(b->d_ode, ode.data(), ode.size() * sizeof(OdeInst), hipMemcpyHostToDevice, b->stream);
+    // rows before t = 0 are read as zeros: every ring and diagonal copy cleared
+    if (e == hipSuccess && launch_clear_batch(b->d_tab, n, b->stream)) e = hipErrorLaunchFailure;
     if (e == hipSuccess && launch_clear_status(b->d_status, b->stream)) e = hipErrorLaunchFailure;
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
@@ -270,30 +289,26 @@ int fdtd_batch_set_boundary(fdtd_batch* b)
     if (launch_clear_status(b->d_status, b->stream)) return bfail(b, FDTD_EDEVICE, "status clear failed");
     for (int i = 0; i < b->n; ++i) {
         fdtd_ctx* c = b->c[i];
-        if (c->p.boundary == FDTD_E_DELAY_ODE) {
-            c->boundary_ready = 0;
-            if (launch_boundary_pre(c)) return bfail(b, FDTD_EDEVICE, "instance %d: boundary launch failed", i);
-        } else {
-            int rc = ctx_boundary_enqueue(c);
-            if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(c));
-        }
+        c->boundary_ready = 0;
+        if (c->p.boundary == FDTD_E_DELAY_ODE) continue;
+        int rc = ctx_boundary_enqueue(c);
+        if (rc) return bfail(b, rc, "instance %d: %s", i, fdtd_last_error(c));
     }
-    if (b->n_ode) {
-        if (launch_E_ode(b->d_ode, b->n_ode, b->stream))
-            return bfail(b, FDTD_EDEVICE, "delay-equation boundary launch failed");
-        for (int i = 0; i < b->n; ++i) {
-            fdtd_ctx* c = b->c[i];
-            if (c->p.boundary != FDTD_E_DELAY_ODE) continue;
-            if (launch_E_from_G(c) || launch_boundary_post(c))
-                return bfail(b, FDTD_EDEVICE, "instance %d: boundary launch failed", i);
-        }
+    // the delay-equation boundaries of all instances at once; e0 and mu of
+    // stimulated emission instance by instance after them
+    if (b->n_ode && launch_boundary_batch(b->d_ode, b->n_ode, b->stream))
+        return bfail(b, FDTD_EDEVICE, "delay-equation boundary launch failed");
+    for (int i = 0; i < b->n; ++i) {
+        fdtd_ctx* c = b->c[i];
+        if (c->p.boundary != FDTD_E_DELAY_ODE || !c->E0) continue;
+        if (launch_e0(c) || launch_mu_rows(c, 0, 0, c->stream))
+            return bfail(b, FDTD_EDEVICE, "instance %d: boundary launch failed", i);
     }
     std::vector<int> st(b->n, 0);
-    for (int i = 0; i < b->n; ++i) {
-        hipError_t e = hipMemcpyAsync(&st[i], b->c[i]->b.status, sizeof(int), hipMemcpyDeviceToHost, b->stream);
-        if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "status copy failed: %s", hipGetErrorString(e));
-    }
-    hipError_t e = hipStreamSynchronize(b->stream);
+    if (launch_gather_status(b->d_tab, b->n, b->d_stat, b->stream))
+        return bfail(b, FDTD_EDEVICE, "status gather failed");
+    hipError_t e = hipMemcpyAsync(st.data(), b->d_stat, (size_t)b->n * sizeof(int), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "boundary kernels failed: %s", hipGetErrorString(e));
     for (int i = 0; i < b->n; ++i) {
         int rc = ctx_boundary_status(b->c[i], st[i]);

@@ -151,10 +151,8 @@ __device__ inline double phi_mass_below(const Packet& pk, double y)
 }
 
 // phi on the grid, the drive per row, and row 0's share of int |psi|^2
-__global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
+__device__ inline void tables_row(const Geom& g, const Packet& pk, const Bufs& b, int64_t nblk, int64_t q)
 {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q > g.Nt) return;
     b.Phi[q] = phi_in(pk, -g.a - (double)q * g.Delta);
     cd d = mk(0.0, 0.0);
     if (q >= 1) {
@@ -167,6 +165,13 @@ __global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
     b.Drv[q] = d;
     // partial sums of row 0 (only column 0 can be non-zero there)
     if (q < nblk) b.Ppart[q] = 0.0;
+}
+
+__global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > g.Nt) return;
+    tables_row(g, pk, b, nblk, q);
 }
 
 // source of E in k_E: computed here, copied from Ebuf, or formed from the
@@ -201,11 +206,9 @@ __global__ __launch_bounds__(64) void k_E_part(Geom g, Packet pk, Bufs b, int nk
     if (range_flag) atomicOr(b.status, STATUS_GAMMA_RANGE);
 }
 
-__global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
-                    int nk, double k_lo, double hk)
+__device__ inline void e_row(const Geom& g, const Packet& pk, const Bufs& b, int from_host, int nk, double k_lo,
+                             double hk, int64_t r)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > g.Nt) return;
     int range_flag = 0;
     cd E;
     if (from_host == E_COPY) {
@@ -243,7 +246,71 @@ __global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_ho
         cd v = b.Phi[0] * Et;
         b.Ppart[0] = 0.5 * norm2(v);
     }
+    (void)k_lo;
+    (void)hk;
+}
+
+__global__ __launch_bounds__(64) void k_E(Geom g, Packet pk, Bufs b, int from_host, int64_t nblk,
+                    int nk, double k_lo, double hk)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > g.Nt) return;
+    e_row(g, pk, b, from_host, nk, k_lo, hk, r);
     (void)nblk;
+}
+
+// The delay-equation boundary of a whole batch, one instance per blockIdx.y
+// (tab holds the instances in any order), BB_X workgroups per instance
+// striding over its rows: the status word and the tables (k_tables), E from
+// G (k_E's E_FROM_G, or E_COPY for the stimulated family), then row 0 of the
+// ring and of the diagonal copy (launch_boundary_post).
+constexpr int BB_X = 8;
+constexpr int BB_THREADS = 128;
+
+__global__ __launch_bounds__(BB_THREADS) void k_tables_batch(const OdeInst* __restrict__ tab)
+{
+    const OdeInst& e = tab[blockIdx.y];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *e.b.status = 0;
+    for (int64_t q = (int64_t)blockIdx.x * BB_THREADS + threadIdx.x; q <= e.g.Nt; q += (int64_t)BB_X * BB_THREADS)
+        tables_row(e.g, e.pk, e.b, e.nblk, q);
+}
+
+__global__ __launch_bounds__(BB_THREADS) void k_E_batch(const OdeInst* __restrict__ tab)
+{
+    const OdeInst& e = tab[blockIdx.y];
+    const int mode = e.pk.incident == FDTD_INC_EXP1 ? E_COPY : E_FROM_G;
+    for (int64_t r = (int64_t)blockIdx.x * BB_THREADS + threadIdx.x; r <= e.g.Nt; r += (int64_t)BB_X * BB_THREADS)
+        e_row(e.g, e.pk, e.b, mode, 0, 0.0, 0.0, r);
+}
+
+__global__ __launch_bounds__(BB_THREADS) void k_post_batch(const OdeInst* __restrict__ tab)
+{
+    const OdeInst& e = tab[blockIdx.y];
+    for (int64_t j = (int64_t)blockIdx.x * BB_THREADS + threadIdx.x; j < e.g.C; j += (int64_t)BB_X * BB_THREADS) {
+        e.b.ring[j] = mk(0.0, 0.0);
+        if (j >= 1 && j <= e.g.D) e.b.Md[(e.g.D - j) * e.g.Mc + j] = mk(0.0, 0.0);
+    }
+}
+
+// the ring and the diagonal copy of every instance of a batch to zero
+// (launch_clear), CLR_X workgroups per instance
+constexpr int CLR_X = 16;
+
+__global__ __launch_bounds__(256) void k_clear_batch(const BInst* __restrict__ tab)
+{
+    const BInst& e = tab[blockIdx.y];
+    const int64_t n = e.g.R * e.g.C, nm = e.g.R * e.g.Mc;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)CLR_X * 256)
+        e.b.ring[i] = mk(0.0, 0.0);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nm; i += (int64_t)CLR_X * 256)
+        e.b.Md[i] = mk(0.0, 0.0);
+}
+
+// every instance's status word into out[e.index]
+__global__ void k_gather_status(const BInst* __restrict__ tab, int n, int* __restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[tab[i].index] = *tab[i].b.status;
 }
 
 // The delay equation G' = -W G + (Gamma/2) G(t - 2a) + phi(-a - t), G = 0
@@ -409,6 +476,30 @@ int launch_e0(fdtd_ctx* c)
 {
     hipLaunchKernelGGL(k_E0, dim3((unsigned)((c->g.Nt + 64) / 64)), dim3(64), 0, c->stream, c->g, c->pk, c->E0,
                        c->b.status);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_boundary_batch(const OdeInst* d_tab, int n, hipStream_t s)
+{
+    if (n <= 0) return FDTD_OK;
+    hipLaunchKernelGGL(k_tables_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
+    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(64), 0, s, d_tab);
+    hipLaunchKernelGGL(k_E_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
+    hipLaunchKernelGGL(k_post_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_clear_batch(const BInst* d_tab, int n, hipStream_t s)
+{
+    if (n <= 0) return FDTD_OK;
+    hipLaunchKernelGGL(k_clear_batch, dim3(CLR_X, (unsigned)n), dim3(256), 0, s, d_tab);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+int launch_gather_status(const BInst* d_tab, int n, int* d_out, hipStream_t s)
+{
+    if (n <= 0) return FDTD_OK;
+    hipLaunchKernelGGL(k_gather_status, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d_tab, n, d_out);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 

@@ -109,6 +109,7 @@ struct OdeInst {
     Geom g;
     Packet pk;
     Bufs b;
+    int64_t nblk;        // the march's workgroups per row (row 0's partial sums)
 };
 
 // Work decomposition of the blocked march (fixed per context).
@@ -259,6 +260,13 @@ struct BInst {
 };
 
 int launch_block_batch(const BInst* d_tab, int n_active, int64_t k, int nb, hipStream_t s);
+// a batch's set-up in bulk: the rings and diagonal copies to zero; the whole
+// delay-equation boundary of the instances in d_ode (status, tables, G, E,
+// row 0; not e0 and mu of stimulated emission); every status word into
+// d_out[index]
+int launch_clear_batch(const BInst* d_tab, int n, hipStream_t s);
+int launch_boundary_batch(const OdeInst* d_ode, int n, hipStream_t s);
+int launch_gather_status(const BInst* d_tab, int n, int* d_out, hipStream_t s);
 // the same check over every row of every instance of a batch (each
 // instance's status word, and `batch_status` for the whole batch)
 int launch_check_batch(const BInst* d_tab, int n, int* batch_status, hipStream_t s);
@@ -278,9 +286,18 @@ int launch_pe_sample_batch(const BInst* d_tab, int n, int64_t n_samples, const d
 cd chi0_coefficient(const fdtd_params* p);
 
 // Internal context life cycle, shared by the one-instance and batched ABIs.
+// With a CtxDefer (one-packet families only) ctx_create enqueues nothing:
+// the caller clears the ring and the diagonal copy, uploads the boundary's
+// step weights (*h_tab) to d_tab, which the context's tables point at, and
+// keeps the launch record (*h_inst) for its own delay-equation launches.
+struct CtxDefer {
+    OdeTab* d_tab;
+    OdeTab* h_tab;
+    OdeInst* h_inst;
+};
 int64_t ctx_bytes(const fdtd_params* p, const PlanKnobs& kn);
 int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n);
 int ctx_create(const fdtd_params* p, const PlanKnobs& kn, void* d_ws, size_t bytes, hipStream_t s, fdtd_ctx** out,
-               char* why, size_t n);
+               char* why, size_t n, const CtxDefer* defer = nullptr);
 int ctx_boundary_enqueue(fdtd_ctx* c);          // boundary kernels without waiting
 int ctx_boundary_status(fdtd_ctx* c, int st);    // turn the device status word into an error (sets c->err)
