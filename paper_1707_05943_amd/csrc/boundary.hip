@@ -315,52 +315,83 @@ __global__ void k_gather_status(const BInst* __restrict__ tab, int n, int* __res
 
 // The delay equation G' = -W G + (Gamma/2) G(t - 2a) + phi(-a - t), G = 0
 // for t <= 0 (stimulated emission: no phi, G(0) = 1), stepped over t_rho =
-// rho Delta with the collocation weights of OdeTab.  One workgroup of one
-// wave per instance; lane i < ODE_P owns node i of every step and keeps that
-// node's values of the last D+1 steps in Gn (it reads back only what it wrote
-// itself), every lane carries G(t_rho).  G(t_r) goes to Ebuf[r].
-__global__ __launch_bounds__(64) void k_E_ode(const OdeInst* __restrict__ tab)
+// rho Delta with the collocation weights of OdeTab: with the forcing f_j of
+// step rho at its nodes tau_j,
+//   G(t_rho + tau_i) = ew_i G(t_rho) + sum_j M_ij f_j   (i < P: the nodes,
+//   i = P: the end of the step, G(t_{rho+1})),
+// and f_j = (Gamma/2) G(t_rho - 2a + tau_j) + phi(-a - t_rho - tau_j), the
+// node values of step rho - D.  The forcing of K <= D consecutive steps
+// needs only node values of earlier rounds, so one round of K steps forms
+// the K P forcing values and the K (P + 1) sums S_i = sum_j M_ij f_j in
+// parallel; only G(t_{rho+1}) = ew_P G(t_rho) + S_P is serial, and then the
+// node values ew_i G(t_rho) + S_i of the K steps again in parallel.  One
+// workgroup per instance; node values of the last D + 1 steps in Gn
+// (row rho mod (D + 1)); G(t_r) goes to Ebuf[r].
+constexpr int ODE_THREADS = 256;
+constexpr int ODE_K = ODE_THREADS / ODE_P;          // steps per round (at most D)
+
+__global__ __launch_bounds__(ODE_THREADS) void k_E_ode(const OdeInst* __restrict__ tab)
 {
     const OdeInst& e = tab[blockIdx.x];
     const Geom& g = e.g;
     const Packet& pk = e.pk;
     const Bufs& b = e.b;
     const OdeTab* T = b.ode;
-    __shared__ cd f[2][ODE_P];
-    const int l = threadIdx.x;
+    __shared__ cd M[ODE_P + 1][ODE_P];
+    __shared__ cd ew[ODE_P + 1];
+    __shared__ double tau[ODE_P];
+    __shared__ cd f[ODE_K][ODE_P];
+    __shared__ cd S[ODE_K][ODE_P + 1];
+    __shared__ cd Gs[ODE_K + 1];
+    const int t = threadIdx.x;
     const int64_t D = g.D, Nt = g.Nt, R = D + 1;
     const double hg = 0.5 * g.Gamma;
     const int stim = pk.incident == FDTD_INC_EXP1;
-    const int li = l < ODE_P ? l : 0;
-    cd Mi[ODE_P], Me[ODE_P];
-    #pragma unroll
-    for (int j = 0; j < ODE_P; ++j) {
-        Mi[j] = T->M[li][j];
-        Me[j] = T->M[ODE_P][j];
+    for (int q = t; q < (ODE_P + 1) * ODE_P; q += ODE_THREADS) M[q / ODE_P][q % ODE_P] = T->M[q / ODE_P][q % ODE_P];
+    if (t <= ODE_P) ew[t] = T->ew[t];
+    if (t < ODE_P) tau[t] = T->tau[t];
+    if (t == 0) {
+        Gs[0] = stim ? mk(1.0, 0.0) : mk(0.0, 0.0);
+        b.Ebuf[0] = Gs[0];
     }
-    const cd ewi = T->ew[li], ewe = T->ew[ODE_P];
-    const double tau = T->tau[li];
-    cd G = stim ? mk(1.0, 0.0) : mk(0.0, 0.0);
-    if (l == 0) b.Ebuf[0] = G;
-    for (int64_t rho = 0; rho < Nt; ++rho) {
-        const int par = (int)(rho & 1);
-        if (l < ODE_P) {
+    const int K = D < ODE_K ? (int)D : ODE_K;
+    __syncthreads();
+    for (int64_t r0 = 0; r0 < Nt; r0 += K) {
+        const int kn = Nt - r0 < K ? (int)(Nt - r0) : K;
+        // forcing of steps r0..r0+kn-1 (node values of steps <= r0 - 1)
+        if (t < kn * ODE_P) {
+            const int k = t / ODE_P, j = t % ODE_P;
+            const int64_t rho = r0 + k;
             cd fo = mk(0.0, 0.0);
-            if (rho >= D) fo = hg * b.Gn[((rho - D) % R) * ODE_P + l];
-            if (!stim) fo += phi_in(pk, -g.a - (double)rho * g.Delta - tau);
-            f[par][l] = fo;
+            if (rho >= D) fo = hg * b.Gn[((rho - D) % R) * ODE_P + j];
+            if (!stim) fo += phi_in(pk, -g.a - (double)rho * g.Delta - tau[j]);
+            f[k][j] = fo;
         }
         __syncthreads();
-        cd ai = ewi * G, ae = ewe * G;
-        #pragma unroll
-        for (int j = 0; j < ODE_P; ++j) {
-            const cd fj = f[par][j];
-            ai += Mi[j] * fj;
-            ae += Me[j] * fj;
+        for (int q = t; q < kn * (ODE_P + 1); q += ODE_THREADS) {
+            const int k = q / (ODE_P + 1), i = q % (ODE_P + 1);
+            cd acc = mk(0.0, 0.0);
+            #pragma unroll
+            for (int j = 0; j < ODE_P; ++j) acc += M[i][j] * f[k][j];
+            S[k][i] = acc;
         }
-        if (l < ODE_P) b.Gn[(rho % R) * ODE_P + l] = ai;
-        G = ae;
-        if (l == 0) b.Ebuf[rho + 1] = G;
+        __syncthreads();
+        if (t == 0) {
+            cd G = Gs[0];
+            for (int k = 0; k < kn; ++k) {
+                G = ew[ODE_P] * G + S[k][ODE_P];
+                Gs[k + 1] = G;
+                b.Ebuf[r0 + k + 1] = G;
+            }
+        }
+        __syncthreads();
+        if (t < kn * ODE_P) {
+            const int k = t / ODE_P, i = t % ODE_P;
+            b.Gn[((r0 + k) % R) * ODE_P + i] = ew[i] * Gs[k] + S[k][i];
+        }
+        __syncthreads();
+        if (t == 0) Gs[0] = Gs[kn];
+        __syncthreads();
     }
 }
 
@@ -483,7 +514,7 @@ int launch_boundary_batch(const OdeInst* d_tab, int n, hipStream_t s)
 {
     if (n <= 0) return FDTD_OK;
     hipLaunchKernelGGL(k_tables_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
-    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(64), 0, s, d_tab);
+    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(ODE_THREADS), 0, s, d_tab);
     hipLaunchKernelGGL(k_E_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
     hipLaunchKernelGGL(k_post_batch, dim3(BB_X, (unsigned)n), dim3(BB_THREADS), 0, s, d_tab);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
@@ -505,7 +536,7 @@ int launch_gather_status(const BInst* d_tab, int n, int* d_out, hipStream_t s)
 
 int launch_E_ode(const OdeInst* d_tab, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(64), 0, s, d_tab);
+    hipLaunchKernelGGL(k_E_ode, dim3((unsigned)n), dim3(ODE_THREADS), 0, s, d_tab);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
