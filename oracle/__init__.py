@@ -16,6 +16,9 @@ Parity status of each part (what pins it, see tests/test_oracle_*.py):
   * march (HYBRID reads)       -- the literal micro-oracle; the micro-oracle in
     turn converges to the exact solution in x <= -a (paper's test 1) and
     conserves the two-excitation probability as Delta -> 0
+  * march with the paper's own reads (march_diag) -- the micro-oracle's
+    paper_diag mode; second-order convergence to the exact solution in
+    x <= -a (the paper's test 1) and to the hybrid march right of -a
   * chi readout, Eq. (2)       -- the micro-oracle's full-grid Eq. (2)
   * mu, lambda, App. D (nm.py) -- conservation of the one-excitation sector,
     the exact value at t = 0, the uncoupled limit
@@ -70,6 +73,7 @@ def _load():
     lib.orc_E_quad_arr.argtypes = [P(OrcParams), i64, vp, vp]
     lib.orc_Jn_quad_arr.argtypes = [P(OrcParams), ctypes.c_int, i64, vp, vp]
     lib.orc_phi_arr.argtypes = [P(OrcParams), i64, vp, vp]
+    lib.orc_march_diag.argtypes = [P(OrcParams), vp, i64, vp, vp, i64, vp]
     lib.orc_phi_mass_below_arr.argtypes = [P(OrcParams), i64, vp, vp]
     lib.orc_E_table.argtypes = [P(OrcParams), ctypes.c_int, vp]
     lib.orc_march.argtypes = [P(OrcParams), vp, vp, vp, vp, i64, i64, vp, vp, i64, vp]
@@ -218,6 +222,32 @@ def march(inst, E: np.ndarray | None = None, *, chi_rows=(), n_tau: int = 0, sna
     if rc != 0:
         raise RuntimeError(f"oracle march failed ({rc}): a read broke the ring's lag bound")
     return {"E": E, "pe": pe, "ring": ring, "chi": chi, "snaps": snaps}
+
+
+def march_diag(inst, diag_cols: int, E: np.ndarray | None = None, *, snap_rows=(), want_pe: bool = True) -> dict:
+    """The march with the paper's own reads: diag_cols columns left of and at
+    x = -a (columns 1-diag_cols..0) are marched too and read back wherever
+    Eq. (1) reaches them; only points left of them take the exact solution.
+    Every row is kept (memory (Nt+1)(Nx+diag_cols)16 B).  Returns a dict
+    with lo (the first marched column), pe (P_e(t_r), column 0 marched) and
+    snaps (columns lo..Nx of the listed rows)."""
+    lib = _load()
+    p = params(inst)
+    if E is None:
+        E = E_table(inst)
+    E = np.ascontiguousarray(E, dtype=np.complex128)
+    assert E.shape == (p.Nt + 1,)
+    lo = 1 - int(diag_cols)
+    W = p.Nx - lo + 1
+    pe = np.empty(p.Nt + 1, np.float64) if want_pe else None
+    sr = np.ascontiguousarray(np.asarray(snap_rows, dtype=np.int64))
+    snaps = np.empty((len(sr), W), np.complex128)
+    nul = ctypes.c_void_p(0)
+    rc = lib.orc_march_diag(ctypes.byref(p), _ptr(E), int(diag_cols), _ptr(pe) if pe is not None else nul,
+                            _ptr(sr) if len(sr) else nul, len(sr), _ptr(snaps) if len(sr) else nul)
+    if rc != 0:
+        raise RuntimeError(f"oracle diag march failed ({rc})")
+    return {"E": E, "lo": lo, "pe": pe, "snaps": snaps}
 
 
 def chi0(inst, x1, x2):

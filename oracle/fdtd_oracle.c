@@ -501,6 +501,12 @@ typedef struct {
     cplx *ring;              /* (D+2) rows of Nx+1 columns; row rho in slot rho mod (D+2) */
     int64_t cur;             /* row being solved */
     int fault;               /* set when a read violates the ring's lag bound */
+    /* the paper's own reads (orc_march_diag): columns lo..Nx (lo <= 0) are
+     * marched and kept for every row; only columns left of lo are read from
+     * the exact solution.  NULL in the hybrid march. */
+    cplx *hist;              /* (Nt+1) rows of Nx - lo + 1 columns */
+    int64_t lo;
+    int64_t cur_col;         /* column being solved in row cur */
 } orc_state;
 
 /* exact solution in x <= -a (Eq. 12 for identical photons, Eq. 8 for
@@ -518,6 +524,11 @@ static cplx psi_at(orc_state *s, int64_t i, int64_t rho)
 {
     const orc_params *p = s->p;
     if (rho < 0) return 0.0;
+    if (s->hist) {
+        if (i < s->lo) return psi_exact(s, i, rho);
+        if (i > p->Nx || rho > s->cur || (rho == s->cur && i >= s->cur_col)) { s->fault = 1; return NAN; }
+        return s->hist[rho * (p->Nx - s->lo + 1) + (i - s->lo)];
+    }
     if (i <= 0) return psi_exact(s, i, rho);
     if (i > p->Nx) { s->fault = 1; return NAN; }
     int64_t lag = s->cur - rho;
@@ -565,7 +576,7 @@ static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1,
      * columns -j and -j+1; -x is midway between D-j and D-j+1.
      * theta(x_c + a) holds for every j >= 1; theta(0) = 1 at r = j. */
     cplx src = 0.0;
-    if (r - j >= 0) src += bar(s, -j, r - j) - bar(s, D - j, r - j);
+    if (j >= 1 && r - j >= 0) src += bar(s, -j, r - j) - bar(s, D - j, r - j);
     /* source 2: [psi(2a-x, t-x+a) - psi(-x, t-x+a)] theta(x-a) theta(t-x+a).
      * t - x + a = (r - j + D) Delta; 2a - x is midway between 2D-j and
      * 2D-j+1; theta(x_c - a) holds iff j >= D+1. */
@@ -691,7 +702,7 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
     const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt, R = D + 2, C = Nx + 1;
     const int two = two_photons(p);
     orc_params ph1 = two ? photon(p, 1) : *p, ph2 = two ? photon(p, 2) : *p;
-    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0 };
+    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0, NULL, 0, 0 };
     s.ring = (cplx *)calloc((size_t)(R * C), sizeof(cplx));
     cplx *phig = (cplx *)malloc(sizeof(cplx) * (size_t)(2 * (Nt + 1)));
     if (!s.ring || !phig) { free(s.ring); free(phig); return -2; }
@@ -748,6 +759,66 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
         }
     }
     free(s.ring);
+    free(phig);
+    return s.fault ? -1 : 0;
+}
+
+/*
+ * The march with the paper's own reads (Sec. 3; its test 1 in Sec. 4): the
+ * diag_cols columns 1-diag_cols .. 0 (x <= -a) are marched too, with the
+ * same square of Eq. (1) (no source terms there: theta(x + a) = 0), and every
+ * read of a marched point takes the marched value; only points left of
+ * column 1-diag_cols take the exact solution (the region the paper fills
+ * with its boundary condition).  Row 0 is the initial condition (the exact
+ * solution in x <= -a, zero right of it).  Every row is kept.
+ *   pe    : out, P_e(t_r) (exact part below -a plus the trapezoid over
+ *           columns 0..Nx, column 0 marched) (may be NULL)
+ *   snaps : out, columns 1-diag_cols .. Nx of each listed row
+ * Returns 0, -1 when a read reached a point not yet solved, -2 when out of
+ * memory.
+ */
+int orc_march_diag(const orc_params *p, const cplx *E, int64_t diag_cols, double *pe,
+                   const int64_t *snap_rows, int64_t n_snap, cplx *snaps)
+{
+    const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt;
+    const int64_t lo = 1 - diag_cols, W = Nx - lo + 1;
+    if (diag_cols < 1 || two_photons(p)) return -3;
+    /* exact reads reach x - t = -a - q Delta with q up to Nt - lo + D + 1 */
+    const int64_t nq = Nt - lo + D + 2;
+    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0, NULL, lo, 0 };
+    s.hist = (cplx *)calloc((size_t)((Nt + 1) * W), sizeof(cplx));
+    cplx *phig = (cplx *)malloc(sizeof(cplx) * (size_t)nq);
+    if (!s.hist || !phig) { free(s.hist); free(phig); return -2; }
+    for (int64_t q = 0; q < nq; ++q) phig[q] = orc_phi(p, -half_a(p) - (double)q * p->Delta);
+    s.phig = phig;
+    s.c_ex = (p->incident == INC_EXP1) ? 1.0 : sqrt(2.0) * cexp(I * p->phase);
+
+    /* row 0: the exact solution at x <= -a, zero right of it */
+    for (int64_t i = lo; i <= 0; ++i) s.hist[i - lo] = psi_exact(&s, i, 0);
+    s.cur = 1;
+    for (int64_t r = 1; r <= Nt; ++r) {
+        s.cur = r;
+        s.cur_col = lo;
+        cplx *row = s.hist + r * W;
+        cplx left = psi_at(&s, lo - 1, r);
+        double tc = ((double)r - 0.5) * p->Delta;
+        cplx drive_row = orc_phi(p, -half_a(p) - tc) - orc_phi(p, half_a(p) - tc);
+        for (int64_t j = lo; j <= Nx; ++j) {
+            s.cur_col = j;
+            cplx u = solve_cell(&s, j, r, left, drive_row, 0.0);
+            row[j - lo] = u;
+            left = u;
+        }
+        if (s.fault) break;
+    }
+    if (!s.fault) {
+        s.cur = Nt + 1;
+        s.cur_col = lo;
+        for (int64_t r = 0; pe && r <= Nt; ++r) pe[r] = pe_row(&s, r);
+        for (int64_t q = 0; q < n_snap; ++q)
+            for (int64_t j = lo; j <= Nx; ++j) snaps[q * W + (j - lo)] = s.hist[snap_rows[q] * W + (j - lo)];
+    }
+    free(s.hist);
     free(phig);
     return s.fault ? -1 : 0;
 }
@@ -810,7 +881,7 @@ void orc_chi0_arr(const orc_params *p, int64_t m, const double *x1, const double
 void orc_exact_part_arr(const orc_params *p, const cplx *E, double *out)
 {
     const int64_t Nt = p->Nt;
-    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0 };
+    orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0, NULL, 0, 0 };
     if (two_photons(p)) s.E2 = E + (Nt + 1);
     for (int64_t r = 0; r <= Nt; ++r) out[r] = exact_part(&s, r);
 }
