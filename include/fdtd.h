@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define FDTD_ABI_VERSION 2u
+#define FDTD_ABI_VERSION 3u
 
 enum fdtd_status {
     FDTD_OK = 0,
@@ -80,6 +80,25 @@ enum fdtd_boundary_method {
     FDTD_E_DELAY_ODE = 1
 };
 
+/* Where the march reads the solution at x <= -a.
+ * FDTD_READ_EXACT: from the partial exact solution c phi(x - t) E(t) (Eqs. 8,
+ *   12); column 0 (x = -a) included.  The marched columns are 1..Nx.
+ * FDTD_READ_PAPER_DIAG: as the paper's program does (Sec. 3): diag_cols
+ *   columns left of and at x = -a (columns 1-diag_cols..0) are marched with
+ *   the same square of Eq. (1), and every read of a marched point, also from
+ *   the source terms of x > -a, which reach x <= -a along diagonals x - t =
+ *   const, takes the marched value; only points left of column 1-diag_cols
+ *   take the exact solution (the region the paper fills with its boundary
+ *   condition).  Every row is kept ((Nt+1) (Nx+diag_cols) complex values), and
+ *   the march advances one row per launch: a test mode (the paper's test 1,
+ *   Sec. 4: the marched x <= -a against the exact solution), not a fast path.
+ *   Rows, the left columns (FDTD_RO_LEFT), P_e and E can be read out; chi and
+ *   the measures of App. D cannot (FDTD_EINVAL).  One-packet families only. */
+enum fdtd_read_mode {
+    FDTD_READ_EXACT = 0,
+    FDTD_READ_PAPER_DIAG = 1
+};
+
 typedef struct fdtd_params {
     uint32_t abi_version;   /* FDTD_ABI_VERSION */
     uint32_t struct_size;   /* sizeof(fdtd_params) */
@@ -100,9 +119,10 @@ typedef struct fdtd_params {
                                   exponential photons (FDTD_INC_EXP2 only): then the incident state is
                                   (A/sqrt 2)[phi1(x1) phi2(x2) + phi1(x2) phi2(x1)] (Eq. 10, A of Eq. 11),
                                   phi_i of Eq. (7) with (k_i, alpha_i), and k, alpha are not used */
-    int32_t reserved;       /* must be 0 */
+    int32_t read_mode;      /* enum fdtd_read_mode */
     double k1, k2;          /* carriers of photon 1 and photon 2 (identical_photons = 0) */
     double alpha1, alpha2;  /* widths of photon 1 and photon 2, units of Gamma (identical_photons = 0) */
+    int64_t diag_cols;      /* FDTD_READ_PAPER_DIAG: marched columns at x <= -a (>= 1); else 0 */
 } fdtd_params;
 
 typedef struct fdtd_ctx fdtd_ctx;
@@ -144,7 +164,8 @@ int fdtd_current_row(const fdtd_ctx *ctx, int64_t *row);
 
 enum fdtd_readout_kind {
     FDTD_RO_ROW = 1,   /* arg = row rho (current-D-1 <= rho <= current); count = Nx+1 values psi(j, rho),
-                          column 0 from the exact solution */
+                          column 0 from the exact solution (FDTD_READ_PAPER_DIAG: any row 0..current,
+                          column 0 marched) */
     FDTD_RO_PE = 2,    /* P_e(t_r) = int |psi(x,t_r)|^2 dx for r = 0..count-1 (count <= current+1), doubles:
                           the exact part x <= -a plus the trapezoid rule over columns 0..Nx */
     FDTD_RO_CHI = 3,   /* chi(x1, x2, t) of Eq. (2) at the current row, detectors x1 = a + Delta,
@@ -162,9 +183,11 @@ enum fdtd_readout_kind {
                           FDTD_ESTATE beyond) */
     FDTD_RO_LAMBDA = 6,/* lambda(t_r) = int |psi(x,t_r)|^2 dx - |e0(t_r)|^2 for r = 0..count-1 (count <= current+1),
                           doubles; the determinant of the dynamical map is |mu|^2 lambda */
-    FDTD_RO_NGEO = 7   /* the geometric measure N_geo (App. D) over [0, t_arg], 0 <= arg <= current (as mu):
+    FDTD_RO_NGEO = 7,  /* the geometric measure N_geo (App. D) over [0, t_arg], 0 <= arg <= current (as mu):
                           the integral of d|det M_t|/dt where it is positive, |det M_t| = |mu|^2 |lambda|
                           taken linear between rows (the sum of its positive increments); count = 1 double */
+    FDTD_RO_LEFT = 8   /* FDTD_READ_PAPER_DIAG only: arg = row rho (0..current); count = diag_cols values
+                          psi(j, rho) for j = 1-diag_cols..0, the marched columns at x <= -a */
 };
 
 /* Copy a readout into dst: a device pointer (dst_on_device = 1, enqueued on
@@ -263,7 +286,9 @@ typedef struct fdtd_batch_opts {
 } fdtd_batch_opts;
 
 /* Device workspace for the batch p[0..n-1] with these options (NULL: the
- * defaults, tmax 32, widest workgroups, graph on). */
+ * defaults, tmax 32, widest workgroups, graph on).  Batches hold one-packet
+ * instances (identical_photons = 1) with read_mode FDTD_READ_EXACT;
+ * FDTD_EINVAL otherwise. */
 int fdtd_batch_workspace_size(const fdtd_params *p, int32_t n, const fdtd_batch_opts *opts, size_t *bytes);
 
 /* Set up the batch in the caller's workspace (device pointer, 256-byte

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdtd.so")
-SOURCES = ["api.hip", "batch.hip", "boundary.hip", "copy.hip", "march_block.hip", "nm.hip", "pair.hip",
+SOURCES = ["api.hip", "batch.hip", "boundary.hip", "copy.hip", "diag.hip", "march_block.hip", "nm.hip", "pair.hip",
            "readout.hip", "surrogate.hip", "sweep.hip"]
 
 HIPCC_FLAGS = [

@@ -78,7 +78,29 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
         snprintf(why, n, "identical_photons must be 0 or 1");
         return FDTD_EINVAL;
     }
-    if (p->reserved != 0) { snprintf(why, n, "reserved must be 0"); return FDTD_EINVAL; }
+    if (p->read_mode != FDTD_READ_EXACT && p->read_mode != FDTD_READ_PAPER_DIAG) {
+        snprintf(why, n, "unknown read mode %d", p->read_mode);
+        return FDTD_EINVAL;
+    }
+    if (p->read_mode == FDTD_READ_EXACT && p->diag_cols != 0) {
+        snprintf(why, n, "diag_cols must be 0 unless read_mode is FDTD_READ_PAPER_DIAG");
+        return FDTD_EINVAL;
+    }
+    if (p->read_mode == FDTD_READ_PAPER_DIAG) {
+        if (p->diag_cols < 1 || p->diag_cols > ((int64_t)1 << 26)) {
+            snprintf(why, n, "FDTD_READ_PAPER_DIAG needs 1 <= diag_cols <= 2^26");
+            return FDTD_EINVAL;
+        }
+        if (p->identical_photons == 0) {
+            snprintf(why, n, "FDTD_READ_PAPER_DIAG is for the one-packet families");
+            return FDTD_EINVAL;
+        }
+        // every row of Nx + diag_cols columns is kept
+        if ((double)(p->Nt + 1) * (double)(p->Nx + p->diag_cols) * 16.0 > 9.0e18) {
+            snprintf(why, n, "FDTD_READ_PAPER_DIAG keeps every row: (Nt+1)(Nx+diag_cols) is too large");
+            return FDTD_EINVAL;
+        }
+    }
     if (p->identical_photons == 0) {
         if (p->incident != FDTD_INC_EXP2) {
             snprintf(why, n, "two different photons are defined for the exponential family (FDTD_INC_EXP2) only");
@@ -111,7 +133,8 @@ int ctx_validate(const fdtd_params* p, const PlanKnobs& kn, char* why, size_t n)
 static int validate(const fdtd_params* p, char* why, size_t n) { return ctx_validate(p, SOLO_KNOBS, why, n); }
 
 struct Layout {
-    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, Epart, E0, Mu, mupart, total;
+    int64_t ring, Md, Et, Phi, Drv, Pex, Ppart, Pe, chi, Ebuf, status, Gn, ode, odeinst, Epart, E0, Mu, mupart, hist,
+        stage, total;
 };
 
 // ring rows: the delay reaches D+1 rows back; the strip runs one block of T
@@ -126,8 +149,10 @@ static Layout layout(const fdtd_params* p, const Plan& P)
     int64_t off = 0;
     L.ring = off; off += align256(R * C * 16);
     L.Md = off; off += align256(R * (p->D + 1) * 16);
+    // the paper's own reads reach phi(-a - q Delta) for q up to Nt + diag_cols + D
+    const int64_t n_phi = p->read_mode == FDTD_READ_PAPER_DIAG ? n + p->diag_cols + p->D : n;
     L.Et = off; off += align256(n * 16);
-    L.Phi = off; off += align256(n * 16);
+    L.Phi = off; off += align256(n_phi * 16);
     L.Drv = off; off += align256(n * 16);
     L.Pex = off; off += align256(n * 8);
     L.Ppart = off; off += align256(n * nblk * 8);
@@ -149,6 +174,11 @@ static Layout layout(const fdtd_params* p, const Plan& P)
         L.E0 = off; off += align256(n * 16);
         L.Mu = off; off += align256(n * 16);
         L.mupart = off; off += align256(n * NM_BLOCKS * 16);
+    }
+    L.hist = L.stage = -1;
+    if (p->read_mode == FDTD_READ_PAPER_DIAG) {
+        L.hist = off; off += align256(n * (p->Nx + p->diag_cols) * 16);
+        L.stage = off; off += align256(p->diag_cols * 16);
     }
     L.total = off;
     return L;
@@ -336,6 +366,9 @@ static int march_setup(fdtd_ctx* c, const fdtd_params* p, const Plan& P, const L
     c->E0 = L.E0 >= 0 ? (cd*)(base + L.E0) : nullptr;
     c->Mu = L.Mu >= 0 ? (cd*)(base + L.Mu) : nullptr;
     c->mupart = L.mupart >= 0 ? (cd*)(base + L.mupart) : nullptr;
+    b.hist = L.hist >= 0 ? (cd*)(base + L.hist) : nullptr;
+    c->stage = L.stage >= 0 ? (cd*)(base + L.stage) : nullptr;
+    c->dc = p->read_mode == FDTD_READ_PAPER_DIAG ? p->diag_cols : 0;
     c->mu_row = -1;
     c->row = -1;
     c->strip_row = -1;
@@ -579,6 +612,16 @@ constexpr int64_t MU_ROWS = 256;
 
 static int march_to(fdtd_ctx* c, int64_t target)
 {
+    if (c->dc) {
+        // the paper's own reads: one launch per row over every marched column
+        const int64_t first = c->row + 1;
+        for (int64_t r = first; r <= target; ++r) {
+            int rc = launch_diag_row(c, r);
+            if (rc) return rc;
+        }
+        c->row = c->strip_row = target;
+        return launch_check_rows(c, first, target);
+    }
     const int64_t T = c->plan.T, Nt = c->p.Nt, R = c->g.R;
     const int64_t first = c->row + 1;                 // rows this call completes: first..target
     int64_t p0 = -1, p1 = -1;     // complete rows waiting for their row sums (mu; |psi_a + psi_b|^2)
@@ -670,7 +713,7 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
     switch (what) {
     case FDTD_RO_ROW:
         if (count != c->p.Nx + 1) return fail(c, FDTD_ESIZE, "a row has Nx+1 = %lld values", (long long)(c->p.Nx + 1));
-        if (arg < 0 || arg > c->row || arg < c->row - (c->p.D + 1))
+        if (arg < 0 || arg > c->row || (!c->dc && arg < c->row - (c->p.D + 1)))
             return fail(c, FDTD_ESTATE, "row %lld is not held (current %lld)", (long long)arg, (long long)c->row);
         // stage through the chi scratch (it holds Nx+1 values)
         rc = c->pair ? launch_row_pair(c, arg, dst_on_device ? (cd*)dst : c->b.chi)
@@ -686,7 +729,17 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         if (dst_on_device) return rc ? fail(c, rc, "launch failed") : FDTD_OK;
         src = c->b.Pe;
         break;
+    case FDTD_RO_LEFT:
+        if (!c->dc) return fail(c, FDTD_EINVAL, "the left columns are marched with FDTD_READ_PAPER_DIAG only");
+        if (count != c->dc) return fail(c, FDTD_ESIZE, "the left columns are diag_cols = %lld values", (long long)c->dc);
+        if (arg < 0 || arg > c->row)
+            return fail(c, FDTD_ESTATE, "row %lld is not marched (current %lld)", (long long)arg, (long long)c->row);
+        rc = launch_diag_copy(c, arg, 1 - c->dc, c->dc, dst_on_device ? (cd*)dst : c->stage);
+        if (dst_on_device) return rc ? fail(c, FDTD_EDEVICE, "launch failed") : FDTD_OK;
+        src = c->stage;
+        break;
     case FDTD_RO_CHI:
+        if (c->dc) return fail(c, FDTD_EINVAL, "chi is not read out with FDTD_READ_PAPER_DIAG");
         if (count > c->p.Nx - c->p.D) return fail(c, FDTD_ESIZE, "at most Nx-D = %lld detector separations",
                                                   (long long)(c->p.Nx - c->p.D));
         rc = c->pair ? launch_chi_pair(c, c->row, count, dst_on_device ? (cd*)dst : c->b.chi)
@@ -695,6 +748,7 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         src = c->b.chi;
         break;
     case FDTD_RO_MU:
+        if (c->dc) return fail(c, FDTD_EINVAL, "the measures of App. D are not read out with FDTD_READ_PAPER_DIAG");
         if (!c->mupart) return fail(c, FDTD_EINVAL, "mu is defined for stimulated emission (FDTD_INC_EXP1) only");
         if (count > c->mu_row + 1)
             return fail(c, FDTD_ESTATE, "mu holds %lld rows (fdtd_march accumulates it, batches do not)",
@@ -704,6 +758,7 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         src = c->Mu;
         break;
     case FDTD_RO_LAMBDA:
+        if (c->dc) return fail(c, FDTD_EINVAL, "the measures of App. D are not read out with FDTD_READ_PAPER_DIAG");
         esz = 8;
         if (!c->E0) return fail(c, FDTD_EINVAL, "lambda is defined for stimulated emission (FDTD_INC_EXP1) only");
         if (count > c->row + 1) return fail(c, FDTD_ESTATE, "only %lld rows marched", (long long)(c->row + 1));
@@ -712,6 +767,7 @@ int fdtd_readout(fdtd_ctx* c, int32_t what, int64_t arg, void* dst, int64_t coun
         src = c->b.Pe;
         break;
     case FDTD_RO_NGEO:
+        if (c->dc) return fail(c, FDTD_EINVAL, "the measures of App. D are not read out with FDTD_READ_PAPER_DIAG");
         esz = 8;
         if (!c->mupart) return fail(c, FDTD_EINVAL, "N_geo is defined for stimulated emission (FDTD_INC_EXP1) only");
         if (count != 1) return fail(c, FDTD_ESIZE, "N_geo is one value");

@@ -101,6 +101,10 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
             snprintf(why, nwhy, "two different photons (identical_photons = 0) are marched one instance at a time");
             rc = FDTD_EINVAL;
         }
+        if (!rc && p[i].read_mode != FDTD_READ_EXACT) {
+            snprintf(why, nwhy, "FDTD_READ_PAPER_DIAG is marched one instance at a time");
+            rc = FDTD_EINVAL;
+        }
         if (rc) {
             char tmp[256];
             snprintf(tmp, sizeof tmp, "instance %d: %s", i, why);

@@ -167,6 +167,14 @@ __device__ inline void tables_row(const Geom& g, const Packet& pk, const Bufs& b
     if (q < nblk) b.Ppart[q] = 0.0;
 }
 
+// phi(-a - q Delta) for q0 <= q <= q1 (the paper's own reads reach x - t
+// beyond -a - Nt Delta)
+__global__ void k_phi_tail(Geom g, Packet pk, Bufs b, int64_t q0, int64_t q1)
+{
+    const int64_t q = q0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q <= q1) b.Phi[q] = phi_in(pk, -g.a - (double)q * g.Delta);
+}
+
 __global__ void k_tables(Geom g, Packet pk, Bufs b, int64_t nblk)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -540,6 +548,14 @@ int launch_E_ode(const OdeInst* d_tab, int n, hipStream_t s)
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
+int launch_phi_tail(fdtd_ctx* c, int64_t q0, int64_t q1)
+{
+    if (q1 < q0) return FDTD_OK;
+    hipLaunchKernelGGL(k_phi_tail, dim3((unsigned)((q1 - q0 + 256) / 256)), dim3(256), 0, c->stream, c->g, c->pk, c->b,
+                       q0, q1);
+    return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
 int launch_boundary(fdtd_ctx* c, int from_host_E)
 {
     int rc = launch_boundary_pre(c);
@@ -553,7 +569,10 @@ int launch_boundary(fdtd_ctx* c, int from_host_E)
         rc = launch_boundary_E(c, E_COMPUTE);
     }
     if (rc) return rc;
-    return launch_boundary_post(c);
+    rc = launch_boundary_post(c);
+    // the paper's own reads: phi further out and row 0 of every kept column
+    if (!rc && c->dc) rc = launch_diag_setup(c);
+    return rc;
 }
 
 int launch_clear(fdtd_ctx* c)

@@ -102,6 +102,7 @@ struct Bufs {
     cd* Epart;       // series boundary of the Gaussian: partial sums over chunks of Fourier nodes
                      // (EPART_CHUNKS x (Nt+1)); NULL for the other boundaries
     OdeTab* ode;     // its step weights
+    cd* hist;        // FDTD_READ_PAPER_DIAG: every row of columns 1-dc..Nx ((Nt+1) x (Nx+dc)); else NULL
 };
 
 // one instance of a (batched) delay-equation boundary launch
@@ -165,6 +166,11 @@ struct fdtd_ctx {
     fdtd_ctx* pair;
     double* xpart;
     cd c0_pair;
+    // FDTD_READ_PAPER_DIAG (Sec. 3's own reads): dc marched columns at x <=
+    // -a, every row in b.hist, one launch per row; 0 otherwise.  stage holds
+    // dc values for readouts of the left columns into host memory.
+    int64_t dc;
+    cd* stage;
     char err[512];
 };
 
@@ -183,6 +189,13 @@ int launch_E_from_G(fdtd_ctx* c);
 int launch_pe_final(fdtd_ctx* c, int64_t nrows, double* dst);
 int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst);
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst);
+// the march with the paper's own reads (diag.hip): the phi table beyond row
+// Nt and row 0 of every kept column (after the boundary); row r; a copy of
+// `count` columns from column j0 of row rho
+int launch_diag_setup(fdtd_ctx* c);
+int launch_phi_tail(fdtd_ctx* c, int64_t q0, int64_t q1);
+int launch_diag_row(fdtd_ctx* c, int64_t r);
+int launch_diag_copy(fdtd_ctx* c, int64_t rho, int64_t j0, int64_t count, cd* dst);
 int launch_clear(fdtd_ctx* c);
 // non-finite detection over the per-row partial sums of |psi|^2 of rows
 // r0..r1 (every marched value enters them): sets STATUS_MARCH_NONFINITE

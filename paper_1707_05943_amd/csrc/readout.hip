@@ -165,6 +165,7 @@ int launch_chi(fdtd_ctx* c, int64_t r, int64_t count, cd* dst)
 
 int launch_row_readout(fdtd_ctx* c, int64_t rho, cd* dst)
 {
+    if (c->dc) return launch_diag_copy(c, rho, 0, c->g.Nx + 1, dst);    // column 0 marched, every row kept
     hipLaunchKernelGGL(k_row_copy, dim3((unsigned)((c->g.C + 255) / 256)), dim3(256), 0, c->stream, c->g, c->b,
                        rho, dst);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;

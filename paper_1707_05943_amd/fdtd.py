@@ -15,9 +15,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfdtd.so")
 
-FDTD_ABI_VERSION = 2
+FDTD_ABI_VERSION = 3
 INC_PLANE, INC_EXP1, INC_EXP2, INC_GAUSS2 = 1, 2, 3, 4
-RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA, RO_NGEO = 1, 2, 3, 4, 5, 6, 7
+RO_ROW, RO_PE, RO_CHI, RO_E, RO_MU, RO_LAMBDA, RO_NGEO, RO_LEFT = 1, 2, 3, 4, 5, 6, 7, 8
+READ_EXACT, READ_PAPER_DIAG = 0, 1
 E_SERIES, E_DELAY_ODE = 0, 1
 STATUS = {0: "FDTD_OK", -1: "FDTD_EINVAL", -2: "FDTD_ESIZE", -3: "FDTD_ESTATE", -4: "FDTD_EDEVICE",
           -5: "FDTD_ERANGE"}
@@ -43,9 +44,9 @@ class FdtdParams(ctypes.Structure):
                 ("incident", ctypes.c_int32), ("boundary", ctypes.c_int32),
                 ("k", ctypes.c_double), ("alpha", ctypes.c_double), ("x0", ctypes.c_double),
                 ("width", ctypes.c_double), ("phase", ctypes.c_double),
-                ("identical_photons", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("identical_photons", ctypes.c_int32), ("read_mode", ctypes.c_int32),
                 ("k1", ctypes.c_double), ("k2", ctypes.c_double), ("alpha1", ctypes.c_double),
-                ("alpha2", ctypes.c_double)]
+                ("alpha2", ctypes.c_double), ("diag_cols", ctypes.c_int64)]
 
 
 class BatchOpts(ctypes.Structure):
@@ -130,8 +131,9 @@ def params(inst) -> FdtdParams:
                       boundary=int(d.get("boundary", 0)), k=float(d.get("k", 0.0)), alpha=float(d.get("alpha", 0.0)),
                       x0=float(d.get("x0", 0.0)), width=float(d.get("width", 1.0)),
                       phase=float(d.get("phase", 0.0)), identical_photons=int(d.get("identical_photons", 1)),
-                      reserved=0, k1=float(d.get("k1", 0.0)), k2=float(d.get("k2", 0.0)),
-                      alpha1=float(d.get("alpha1", 0.0)), alpha2=float(d.get("alpha2", 0.0)))
+                      read_mode=int(d.get("read_mode", 0)), k1=float(d.get("k1", 0.0)), k2=float(d.get("k2", 0.0)),
+                      alpha1=float(d.get("alpha1", 0.0)), alpha2=float(d.get("alpha2", 0.0)),
+                      diag_cols=int(d.get("diag_cols", 0)))
 
 
 def workspace_size(inst) -> int:
@@ -259,6 +261,10 @@ class Solver:
 
     def pe(self, count: int | None = None) -> np.ndarray:
         return self._ro(RO_PE, 0, self.row + 1 if count is None else count, np.float64)
+
+    def left_values(self, rho: int) -> np.ndarray:
+        """READ_PAPER_DIAG: the marched columns 1-diag_cols..0 of row rho"""
+        return self._ro(RO_LEFT, rho, int(self.p.diag_cols), np.complex128)
 
     def chi(self, count: int) -> np.ndarray:
         return self._ro(RO_CHI, 0, count, np.complex128)

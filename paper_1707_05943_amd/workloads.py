@@ -51,6 +51,8 @@ class Instance:
     k2: float = 0.0
     alpha1: float = 0.0
     alpha2: float = 0.0
+    read_mode: int = 0      # 1: the paper's own reads at x <= -a (diag_cols marched columns there)
+    diag_cols: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -134,6 +136,18 @@ def paper_sets() -> dict:
     ):
         out[inst.name] = inst
     return out
+
+
+def paper_reads(inst: Instance, diag_cols: int | None = None) -> Instance:
+    """The instance marched with the paper's own reads at x <= -a.  The
+    paper's grid spans x/Delta in [-Nx, Nx] about x = -a, and a point reads
+    the delay term D + 1 columns to its left, so the points it can march at
+    x <= -a are the Nx - D columns next to -a (the default); left of them it
+    supplies the exact solution."""
+    d = inst.as_dict()
+    d.update(read_mode=1, diag_cols=int(inst.Nx - inst.D if diag_cols is None else diag_cols),
+             name=f"{inst.name}_paper_reads")
+    return Instance(**d)
 
 
 def with_sizes(inst: Instance, *, Nx: int | None = None, Nt: int | None = None,

@@ -36,7 +36,9 @@ def test_readout_kinds_match_header():
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     enum = dict((k, int(v)) for k, v in re.findall(r"\bFDTD_(RO_[A-Z]+)\s*=\s*(\d+)", txt))
     assert enum == {k: getattr(fdtd, k) for k in enum}
-    assert set(enum) == {"RO_ROW", "RO_PE", "RO_CHI", "RO_E", "RO_MU", "RO_LAMBDA", "RO_NGEO"}
+    assert set(enum) == {"RO_ROW", "RO_PE", "RO_CHI", "RO_E", "RO_MU", "RO_LAMBDA", "RO_NGEO", "RO_LEFT"}
+    modes = dict((k, int(v)) for k, v in re.findall(r"\bFDTD_(READ_[A-Z_]+)\s*=\s*(\d+)", txt))
+    assert modes == {"READ_EXACT": fdtd.READ_EXACT, "READ_PAPER_DIAG": fdtd.READ_PAPER_DIAG}
 
 
 def test_workspace_grows_by_the_measures_for_stimulated_emission():
@@ -63,8 +65,41 @@ def test_surrogate_sizes_on_the_host():
 
 
 def test_params_struct_layout_matches_header():
-    # u32/u32 header + 3 int64 + 3 double + 2 int32 + 5 double + 2 int32 + 4 double
-    assert ctypes.sizeof(fdtd.FdtdParams) == 8 + 24 + 24 + 8 + 40 + 8 + 32
+    # u32/u32 header + 3 int64 + 3 double + 2 int32 + 5 double + 2 int32 + 4 double + int64
+    assert ctypes.sizeof(fdtd.FdtdParams) == 8 + 24 + 24 + 8 + 40 + 8 + 32 + 8
+
+
+def _paper_reads(**kw):
+    d = W.paper_reads(W.Instance(name="pr", Nx=300, D=20, Nt=500, Delta=0.02, omega0=1.5, Gamma=0.3,
+                                 incident=W.INC_PLANE, k=1.5)).as_dict()
+    d.update(kw)
+    return d
+
+
+def test_paper_reads_keep_every_row():
+    """the paper's own reads keep rows 0..Nt of columns 1-diag_cols..Nx, a
+    phi table reaching Nt + diag_cols + D, and diag_cols staging values"""
+    d = _paper_reads()
+    assert d["diag_cols"] == 280
+    plain = dict(d, read_mode=0, diag_cols=0)
+    al = lambda b: (b + 255) // 256 * 256
+    n = d["Nt"] + 1
+    extra = (al(16 * (n + 280 + 20)) - al(16 * n)) + al(16 * n * (300 + 280)) + al(16 * 280)
+    assert fdtd.workspace_size(d) - fdtd.workspace_size(plain) == extra
+
+
+@pytest.mark.parametrize("kw", [dict(diag_cols=0), dict(read_mode=2), dict(read_mode=0),
+                                dict(diag_cols=1 << 27)])
+def test_paper_reads_are_validated(kw):
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.workspace_size(_paper_reads(**kw))
+    assert e.value.code == -1
+
+
+def test_batches_take_the_exact_reads_only():
+    with pytest.raises(fdtd.FdtdError) as e:
+        fdtd.batch_workspace_size([_paper_reads()])
+    assert e.value.code == -1
 
 
 def _two(**kw):
