@@ -104,10 +104,14 @@ __global__ __launch_bounds__(CK_THREADS) void k_check(const double* __restrict__
 extern "C" int sur_encode(const double* d_par, int32_t B, int32_t n, float* d_x, void* hip_stream)
 {
     if (!d_par || !d_x || B < 0 || n < 2) return SUR_EINVAL;
-    if (B == 0) return SUR_OK;
-    hipLaunchKernelGGL(k_encode, dim3((unsigned)((n + 255) / 256), (unsigned)B), dim3(256), 0,
-                       (hipStream_t)hip_stream, d_par, n, d_x);
-    return hipGetLastError() == hipSuccess ? SUR_OK : SUR_EDEVICE;
+    // instances along the grid's y dimension, at most 65535 per launch
+    for (int32_t b0 = 0; b0 < B; b0 += 65535) {
+        const int32_t nb = B - b0 < 65535 ? B - b0 : 65535;
+        hipLaunchKernelGGL(k_encode, dim3((unsigned)((n + 255) / 256), (unsigned)nb), dim3(256), 0,
+                           (hipStream_t)hip_stream, d_par + (int64_t)6 * b0, n, d_x + (int64_t)b0 * n * 8);
+        if (hipGetLastError() != hipSuccess) return SUR_EDEVICE;
+    }
+    return SUR_OK;
 }
 
 extern "C" int sur_check(const double* d_S, const double* d_P2, const double* d_P4, const double* d_P8,
