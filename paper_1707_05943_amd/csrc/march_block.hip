@@ -284,6 +284,20 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;     // raw (unswizzled, stride 0) buffer, 32-bit data
 constexpr int OUT_OF_RANGE = 0x7ffffff0;
 
+// Ring rows are read again D rows later, long after they have left L2:
+// streaming stores (the NT cache policy) keep them from filling it and from
+// the write-back at the kernel's end.  Stores of the diagonal copy, which the
+// mirror reads a block later, stay ordinary.
+constexpr int CPOL_NT = 2;
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_stream(void* p, cd v)
+{
+    d2v x;
+    x.x = v.re;
+    x.y = v.im;
+    __builtin_nontemporal_store(x, reinterpret_cast<d2v*>(p));
+}
+
 __device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, int row_bytes, int64_t cw,
                                            int64_t c_lo, int64_t c_hi, int lane)
 {
@@ -301,7 +315,7 @@ __device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, 
     for (int i = 0; i < K; ++i) {
         const int64_t c = cw + 64 * i + lane;
         const int off = (c >= c_lo && c <= c_hi) ? (int)(c * 16) : OUT_OF_RANGE;
-        __builtin_amdgcn_raw_buffer_store_b128(x[i], rs, off, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(x[i], rs, off, 0, CPOL_NT);
     }
     __builtin_amdgcn_wave_barrier();              // the slot is rewritten by the next row
 }
@@ -629,7 +643,7 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             v = act ? v : zero();
             up[i + 1] = v;
             if (act && j >= S.own_lo) {
-                *reinterpret_cast<cd*>(wp + 16 * i) = v;
+                store_stream(wp + 16 * i, v);
                 const double m2 = norm2(v);
                 pe += (j == g.Nx) ? 0.5 * m2 : m2;
             }
@@ -867,7 +881,7 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             v = act ? v : zero();
             up[i + 1] = v;
             if (act && j >= S.own_lo) {
-                if (S.write_ring) rowp[j] = v;
+                if (S.write_ring) store_stream(&rowp[j], v);
                 if (S.write_md) b.Md[sd * Mc + j] = v;
                 pe += norm2(v);
             }
