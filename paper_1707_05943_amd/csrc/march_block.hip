@@ -115,10 +115,12 @@ __device__ inline cd cpow_u(cd x, int e)
     return r;
 }
 
+// by the second wave (and one thread of the third): the first forms the
+// block's per-row values meanwhile
 __device__ void fill_pow(cd al, Pow& p)
 {
-    const int t = threadIdx.x;
-    if (t < 64) {
+    const int t = (int)threadIdx.x - 64;
+    if (t >= 0 && t < 64) {
         const cd aK = cpow_u(al, K);
         const int l32 = t & 31;
         p.m15[t] = (l32 >= 16) ? cpow_u(aK, l32 - 15) : mk(0.0, 0.0);
@@ -902,21 +904,67 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
     }
 }
 
-// tables of q = r - j over a block for the columns lo..hi-1 and rows ra..rb
-__device__ void fill_tables(const Bufs& b, int64_t D, int far, int64_t qa, int64_t n, cd* tE, cd* tP, cd* tE2,
-                            int t_begin, int t_count)
+// tables of q = r - j over a block for the columns lo..hi-1 and rows ra..rb,
+// by the threads t_begin .. t_begin + t_count - 1.  A thread issues the loads
+// of its first FT_UNROLL entries before it stores any of them, so the set-up
+// waits for one memory round trip, not one per entry (FT_UNROLL t_count
+// covers every table the planner makes: n < TBL with t_count = NT, n < TBL/2
+// with t_count = NT/2, n < TBLN for the near tables); a plain loop takes any
+// entries beyond.
+constexpr int FT_UNROLL = 4;
+static_assert(FT_UNROLL * NT >= TBL && FT_UNROLL * (NT / 2) >= TBL / 2 && FT_UNROLL * NT >= TBLN,
+              "set-up tables in one round of loads");
+
+struct TabEntry {
+    cd e, p, e2;
+};
+
+// Et[q + D] is read only where a table holds it (far: Et[q] - Et[q+D]; near: tE2)
+__device__ __forceinline__ TabEntry table_entry(const Bufs& b, int64_t D, int far, bool e2, int64_t q)
 {
-    for (int64_t t = threadIdx.x - t_begin; t <= n; t += t_count) {
-        if (t < 0) continue;
-        const int64_t q = qa + t;
-        if (far) {
-            tE[t] = et_at(b, q) - et_at(b, q + D);
-            tP[t] = phi_at(b, q);
-        } else {
-            tE[t] = et_at(b, q);
-            tP[t] = phi_at(b, q);
-            if (tE2) tE2[t] = et_at(b, q + D);
+    TabEntry x;
+    const cd eq = et_at(b, q), eqd = (far || e2) ? et_at(b, q + D) : zero();
+    x.e = far ? eq - eqd : eq;
+    x.e2 = eqd;
+    x.p = phi_at(b, q);
+    return x;
+}
+
+// one thread's share of a table: entries u, u + t_count, ... of qa .. qa + n,
+// u = threadIdx.x - t_begin (every thread of the workgroup has one job)
+struct TabJob {
+    int64_t qa, n;
+    cd *tE, *tP, *tE2;
+    int t_begin, t_count, far;
+};
+
+__device__ __forceinline__ void tab_load(const Bufs& b, int64_t D, const TabJob& J, TabEntry (&x)[FT_UNROLL])
+{
+    const int u = (int)threadIdx.x - J.t_begin;
+    #pragma unroll
+    for (int i = 0; i < FT_UNROLL; ++i) {
+        const int64_t t = u + (int64_t)i * J.t_count;
+        x[i] = table_entry(b, D, J.far, J.tE2 != nullptr, J.qa + (t <= J.n ? t : 0));
+    }
+}
+
+__device__ __forceinline__ void tab_store(const Bufs& b, int64_t D, const TabJob& J, const TabEntry (&x)[FT_UNROLL])
+{
+    const int u = (int)threadIdx.x - J.t_begin;
+    #pragma unroll
+    for (int i = 0; i < FT_UNROLL; ++i) {
+        const int64_t t = u + (int64_t)i * J.t_count;
+        if (t <= J.n) {
+            J.tE[t] = x[i].e;
+            J.tP[t] = x[i].p;
+            if (J.tE2) J.tE2[t] = x[i].e2;
         }
+    }
+    for (int64_t t = u + (int64_t)FT_UNROLL * J.t_count; t <= J.n; t += J.t_count) {
+        const TabEntry y = table_entry(b, D, J.far, J.tE2 != nullptr, J.qa + t);
+        J.tE[t] = y.e;
+        J.tP[t] = y.p;
+        if (J.tE2) J.tE2[t] = y.e2;
     }
 }
 
@@ -1037,13 +1085,42 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         S.tP = tab1 + TBL / 2;
     }
 
-    // per-row values of this block, scan constants, tables
+    // tables of the block (in cone mode the two halves of the workgroup fill
+    // the strip's and the cone's; strip tables reach one entry beyond each
+    // end, Phi[q-1] and Phi[q+1]).  Their loads go out first; the per-row
+    // values and the scan constants are formed while they are in flight.
+    TabJob J;
+    if (is_strip) {
+        S.qa -= 1;
+        const bool second = cone && (int)threadIdx.x >= NT / 2;
+        J.far = 0;
+        J.tE2 = nullptr;
+        J.t_begin = second ? NT / 2 : 0;
+        J.t_count = cone ? NT / 2 : NT;
+        J.qa = second ? ra - D - 1 : ra - (c1 - 1) - 1;
+        J.n = second ? P.cone_L0 + (rb - ra) + 2 : (c1 - lo) + (rb - ra) + 2;
+        J.tE = second ? tab0 + TBL / 2 : tab0;
+        J.tP = second ? tab1 + TBL / 2 : tab1;
+    } else {
+        J.far = far;
+        J.tE2 = far ? nullptr : tab2;
+        J.t_begin = 0;
+        J.t_count = NT;
+        J.qa = ra - (c1 - 1);
+        J.n = (c1 - lo) + (rb - ra);
+        J.tE = tab0;
+        J.tP = tab1;
+    }
+    TabEntry tx[FT_UNROLL];
+    tab_load(b, D, J, tx);
+    const int64_t slot_a = ra % g.R;                 // one (scalar) division; R > D + 1 and nrows <= R
     if (threadIdx.x < nrows) {
         const int64_t r = ra + threadIdx.x;
         RowInfo ri;
-        ri.slot = r % g.R;
-        ri.slot_m1 = (r - 1) % g.R;
-        ri.slot_pf = slot_or_neg(r + 1 - D, g.R);
+        ri.slot = slot_a + threadIdx.x < g.R ? slot_a + threadIdx.x : slot_a + threadIdx.x - g.R;
+        ri.slot_m1 = dec_slot(ri.slot, g.R);
+        const int64_t spf = ri.slot + 1 - D;          // (r + 1 - D) mod R, from r mod R
+        ri.slot_pf = (r + 1 - D < 0) ? -1 : (spf < 0 ? spf + g.R : spf);
         ri.half_pr = 0.5 * (phi_at(b, r) + phi_at(b, r - 1));
         ri.half_qr = 0.5 * (phi_at(b, r - D) + phi_at(b, r - D - 1));
         ri.drv = b.Drv[r];
@@ -1060,19 +1137,7 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
         rinfo[threadIdx.x] = ri;
     }
     fill_pow(g.alpha, pw);
-    if (is_strip) {
-        // strip tables reach one entry beyond each end (Phi[q-1], Phi[q+1])
-        S.qa -= 1;
-        if (cone) {
-            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab0, tab1, nullptr, 0, NT / 2);
-            fill_tables(b, D, 0, ra - D - 1, P.cone_L0 + (rb - ra) + 2, tab0 + TBL / 2, tab1 + TBL / 2, nullptr,
-                        NT / 2, NT / 2);
-        } else {
-            fill_tables(b, D, 0, ra - (c1 - 1) - 1, (c1 - lo) + (rb - ra) + 2, tab0, tab1, nullptr, 0, NT);
-        }
-    } else {
-        fill_tables(b, D, far, ra - (c1 - 1), (c1 - lo) + (rb - ra), tab0, tab1, far ? nullptr : tab2, 0, NT);
-    }
+    tab_store(b, D, J, tx);
     // no barrier here: the row loops' prologues issue their loads first and
     // their barrier publishes these tables, rows and powers as well
 
