@@ -147,7 +147,7 @@ def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
     need = max(fdtd.batch_workspace_size(insts, fdtd.batch_opts(t, w)) for t in (32, 16, 8) for w in (0, 768))
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
     t0 = time.perf_counter()
-    best, rate = fdtd.autotune(insts, probe_rows=256, workspace=ws)
+    best, rate = fdtd.autotune(insts, probe_rows=1024, workspace=ws)
     t_tune = time.perf_counter() - t0
     print(f"[bench] batch autotune: tmax={best.tmax} wmax={best.wmax} probe rate {rate:.3g} cells/s "
           f"({t_tune:.1f} s)", file=sys.stderr, flush=True)

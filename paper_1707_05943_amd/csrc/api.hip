@@ -913,10 +913,11 @@ int fdtd_describe(const fdtd_params* p, char* buf, size_t n)
              "{\"T\": %d, \"H\": %d, \"hmax\": %d, \"cone_mode\": %d, \"Gs\": %d, \"Gm\": %d, \"Gn\": %d, "
              "\"strip_w\": %lld, \"near_w\": %lld, \"far_w\": %lld, \"near_end\": %lld, \"cone_L0\": %lld, "
              "\"nwg\": %d, \"nb\": %d, \"scan_stages\": %d, "
-             "\"ring_rows\": %lld, \"alpha_abs\": %.6g, \"threads\": %d, \"cols_per_thread\": %d}",
+             "\"ring_rows\": %lld, \"alpha_abs\": %.6g, \"threads\": %d, \"cols_per_thread\": %d, "
+             "\"stream_stores\": %d}",
              P.T, P.H, P.hmax, P.cone_mode, P.Gs, P.Gm, P.Gn, (long long)P.strip_w, (long long)P.near_w,
              (long long)P.far_w, (long long)P.near_end,
-             (long long)P.cone_L0, P.nwg, P.nb, P.nst, (long long)ring_rows(p, P), cabs_(g.alpha), BM_THREADS, BM_K);
+             (long long)P.cone_L0, P.nwg, P.nb, P.nst, (long long)ring_rows(p, P), cabs_(g.alpha), BM_THREADS, BM_K, P.stream);
     return FDTD_OK;
 }
 

@@ -85,6 +85,7 @@ static PlanKnobs knobs_of(const fdtd_batch_opts& o)
     k.ncu = 1;              // the widest workgroups: the batch, not one instance, fills the chip
     k.tmax = o.tmax;
     k.wmax = o.wmax;
+    k.stream_ok = 0;        // measured: ordinary ring stores are faster for batches of small instances
     return k;
 }
 

@@ -137,6 +137,7 @@ struct Plan {
     int nwg;             // Gs + Gm
     int nb;              // launched blocks (a multiple of 8, >= nwg)
     int nst;             // doubling stages of the within-row scan inside 16-lane rows (2^nst K > H, <= 4)
+    int stream;          // ring rows leave as streaming stores (see make_plan)
 };
 
 struct fdtd_ctx {
@@ -236,8 +237,9 @@ struct PlanKnobs {
     int ncu;
     int tmax;
     int64_t wmax;
+    int stream_ok;       // streaming ring stores allowed (one instance per launch)
 };
-constexpr PlanKnobs SOLO_KNOBS = {256, BM_TMAX, BM_CAP};
+constexpr PlanKnobs SOLO_KNOBS = {256, BM_TMAX, BM_CAP, 1};
 
 int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char* why, size_t n);
 int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1);

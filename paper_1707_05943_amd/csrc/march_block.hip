@@ -286,11 +286,14 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;     // raw (unswizzled, stride 0) buffer, 32-bit data
 constexpr int OUT_OF_RANGE = 0x7ffffff0;
 
-// Ring rows are read again D rows later, long after they have left L2:
-// streaming stores (the NT cache policy) keep them from filling it and from
-// the write-back at the kernel's end.  Stores of the diagonal copy, which the
-// mirror reads a block later, stay ordinary.
+// Ring rows are read again D rows later.  When the grid writes more than the
+// last-level cache holds in between (Plan::stream), they leave as streaming
+// stores (the NT cache policy), which keeps them from filling L2 and from the
+// write-back at the kernel's end; otherwise ordinary stores keep them cached
+// for that read.  Stores of the diagonal copy, which the mirror reads a block
+// later, stay ordinary.
 constexpr int CPOL_NT = 2;
+constexpr double LLC_BYTES = 256.0 * 1024 * 1024;    // MI355X last-level (Infinity) cache
 typedef double d2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void store_stream(void* p, cd v)
 {
@@ -300,6 +303,7 @@ __device__ __forceinline__ void store_stream(void* p, cd v)
     __builtin_nontemporal_store(x, reinterpret_cast<d2v*>(p));
 }
 
+template <bool STREAM>
 __device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, int row_bytes, int64_t cw,
                                            int64_t c_lo, int64_t c_hi, int lane)
 {
@@ -317,7 +321,7 @@ __device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, 
     for (int i = 0; i < K; ++i) {
         const int64_t c = cw + 64 * i + lane;
         const int off = (c >= c_lo && c <= c_hi) ? (int)(c * 16) : OUT_OF_RANGE;
-        __builtin_amdgcn_raw_buffer_store_b128(x[i], rs, off, 0, CPOL_NT);
+        __builtin_amdgcn_raw_buffer_store_b128(x[i], rs, off, 0, STREAM ? CPOL_NT : 0);
     }
     __builtin_amdgcn_wave_barrier();              // the slot is rewritten by the next row
 }
@@ -327,6 +331,7 @@ __device__ __forceinline__ void wave_store(cd* slot, const cd (&v)[K], cd* row, 
 // are the only reads of the ring.  The workgroup's range starts a halo left
 // of its own columns (the trapezoid moves H+1 columns right per row), so the
 // carry into its first column is zero.
+template <bool STREAM>
 __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                          const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
                                          int64_t rb, int H1, int nst, cd (*dstage)[DSTAGE], cd* wslot)
@@ -446,7 +451,7 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
             const double m2 = norm2(v);
             pe += (j < S.own_lo || j > jmax) ? 0.0 : ((j == g.Nx) ? 0.5 * m2 : m2);
         }
-        wave_store(wslot, *reinterpret_cast<const cd(*)[K]>(up + 1), b.ring + (int64_t)uni((int)ri.slot) * C,
+        wave_store<STREAM>(wslot, *reinterpret_cast<const cd(*)[K]>(up + 1), b.ring + (int64_t)uni((int)ri.slot) * C,
                    (int)(C * 16), j0 - K * lane, S.own_lo, jmax, lane);
         pe = wave_sum63(pe);
         if (lane == 63) pe_lds[tau][wv] = pe;
@@ -466,6 +471,7 @@ __device__ __forceinline__ void far_rows(const Geom& g, const Bufs& b, const Pow
 // psi(2D-j+1, q+D) from the diagonal copy for j < 2D, with psi(0, q+D)
 // exact at j = 2D and both exact beyond.  The delay rows, the diagonal-copy
 // rows and (first workgroup) the carry psi(D, r) pass through LDS stages.
+template <bool STREAM>
 __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Pow& pw, cd (*wave_tot)[NW],
                                           const RowInfo* rinfo, double (*pe_lds)[NW], const Seg& S, int64_t ra,
                                           int64_t rb, int H1, int nst, cd (*dstage)[NSTAGE], cd (*mstage)[NSTAGE])
@@ -645,7 +651,8 @@ __device__ __forceinline__ void near_rows(const Geom& g, const Bufs& b, const Po
             v = act ? v : zero();
             up[i + 1] = v;
             if (act && j >= S.own_lo) {
-                store_stream(wp + 16 * i, v);
+                if constexpr (STREAM) store_stream(wp + 16 * i, v);
+                else *reinterpret_cast<cd*>(wp + 16 * i) = v;
                 const double m2 = norm2(v);
                 pe += (j == g.Nx) ? 0.5 * m2 : m2;
             }
@@ -682,7 +689,7 @@ enum StripMode {
 // psi(D-j, q), psi(D-j+1, q) come from the diagonal copy (its rows staged
 // through LDS) or, for the strip's first columns, from the LDS window of the
 // current block.  The table here starts one entry before q = S.qa + 1.
-template <int MODE>
+template <int MODE, bool STREAM>
 __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const Win& W, const Pow& pw,
                                            cd (*wave_tot)[NW], const RowInfo* rinfo, double (*pe_lds)[NW],
                                            const Seg& S, int64_t ra, int64_t rb, int H1, int T, int cone,
@@ -883,7 +890,10 @@ __device__ __forceinline__ void strip_rows(const Geom& g, const Bufs& b, const W
             v = act ? v : zero();
             up[i + 1] = v;
             if (act && j >= S.own_lo) {
-                if (S.write_ring) store_stream(&rowp[j], v);
+                if (S.write_ring) {
+                    if constexpr (STREAM) store_stream(&rowp[j], v);
+                    else rowp[j] = v;
+                }
                 if (S.write_md) b.Md[sd * Mc + j] = v;
                 pe += norm2(v);
             }
@@ -998,6 +1008,7 @@ struct Shared {
 
 // Workgroup w of an instance's launch: the outgoing region over rows m0..m1
 // and the strip over rows s0..s1 (either range may be empty).
+template <bool STREAM>
 __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const Plan& P, int64_t m0, int64_t m1,
                                            int64_t s0, int64_t s1, int w, Shared& sh)
 {
@@ -1152,19 +1163,19 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     // whose D columns fit one wave (it writes its own window)
     const int one_wave_cone = cone && (P.cone_L0 + K - 1) / K <= 64;
     const int one_wave_strip = is_strip && P.cone_mode == 0 && (D + K - 1) / K <= 64;
-    if (far) far_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage, wslot);
+    if (far) far_rows<STREAM>(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.f.dstage, wslot);
     else if (is_strip) {
         if (use_win && S.t0 == 0) {
             if (one_wave_cone || one_wave_strip)
-                strip_rows<SM_WIN>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+                strip_rows<SM_WIN, STREAM>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
             else
-                strip_rows<SM_LATE>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+                strip_rows<SM_LATE, STREAM>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
         } else if (one_wave_cone && S.t0 != 0) {
-            strip_rows<SM_CONE1>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+            strip_rows<SM_CONE1, STREAM>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
         } else {
-            strip_rows<SM_PLAIN>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
+            strip_rows<SM_PLAIN, STREAM>(g, b, W, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.T, cone, P.nst, sh.u.s.mstage);
         }
-    } else near_rows(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
+    } else near_rows<STREAM>(g, b, pw, wave_tot, rinfo, pe_lds, S, ra, rb, H1, P.nst, sh.u.n.dstage, sh.u.n.mstage);
     __syncthreads();
     if (threadIdx.x < nrows) {
         const int tau = threadIdx.x;
@@ -1179,13 +1190,29 @@ __device__ __forceinline__ void block_body(const Geom& g, const Bufs& b, const P
     }
 }
 
-__global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
-                                                       int64_t s0, int64_t s1)
+template <bool STREAM>
+__device__ __forceinline__ void block_entry(const Geom& g, const Bufs& b, const Plan& P, int64_t m0, int64_t m1,
+                                            int64_t s0, int64_t s1)
 {
     __shared__ Shared sh;
     const int bid = blockIdx.x;
     const int w = (bid % 8) * (P.nb / 8) + bid / 8;     // neighbouring column ranges share an XCD
-    block_body(g, b, P, m0, m1, s0, s1, w, sh);
+    block_body<STREAM>(g, b, P, m0, m1, s0, s1, w, sh);
+}
+
+// one instance, ring rows as streaming stores (Plan::stream: grids whose
+// rows leave the last-level cache before they are read again)
+__global__ __launch_bounds__(BM_THREADS) void k_block(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
+                                                       int64_t s0, int64_t s1)
+{
+    block_entry<true>(g, b, P, m0, m1, s0, s1);
+}
+
+// one instance, ordinary ring stores (rows still cached when read again)
+__global__ __launch_bounds__(BM_THREADS) void k_block_cached(Geom g, Bufs b, Plan P, int64_t m0, int64_t m1,
+                                                              int64_t s0, int64_t s1)
+{
+    block_entry<false>(g, b, P, m0, m1, s0, s1);
 }
 
 // Many instances in one launch: launch k advances every instance whose march
@@ -1208,14 +1235,19 @@ __global__ __launch_bounds__(BM_THREADS) void k_block_batch(const BInst* __restr
     if (w >= e.P.nwg || k >= e.launches) return;
     int64_t m0, m1, s0, s1;
     block_rows(e.P.T, e.g.Nt, k, &m0, &m1, &s0, &s1);
-    block_body(e.g, e.b, e.P, m0, m1, s0, s1, w, sh);
+    block_body<false>(e.g, e.b, e.P, m0, m1, s0, s1, w, sh);
 }
 
 }  // namespace
 
 int launch_block(fdtd_ctx* c, int64_t m0, int64_t m1, int64_t s0, int64_t s1)
 {
-    hipLaunchKernelGGL(k_block, dim3(c->plan.nb), dim3(BM_THREADS), 0, c->stream, c->g, c->b, c->plan, m0, m1, s0, s1);
+    if (c->plan.stream)
+        hipLaunchKernelGGL(k_block, dim3(c->plan.nb), dim3(BM_THREADS), 0, c->stream, c->g, c->b, c->plan, m0, m1, s0,
+                           s1);
+    else
+        hipLaunchKernelGGL(k_block_cached, dim3(c->plan.nb), dim3(BM_THREADS), 0, c->stream, c->g, c->b, c->plan, m0,
+                           m1, s0, s1);
     return hipGetLastError() == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
 }
 
@@ -1322,6 +1354,9 @@ int make_plan(const fdtd_params* p, int H, const PlanKnobs& kn, Plan* out, char*
         P.nst = 0;
         while (P.nst < 4 && (1 << P.nst) < look + 1) ++P.nst;
         P.nb = ((P.nwg + 7) / 8) * 8;
+        // streaming ring stores when the rows written between a row's store
+        // and its re-read D rows later exceed the last-level cache
+        P.stream = kn.stream_ok && (double)D * (double)(Nx + 1) * 16.0 > LLC_BYTES;
         *out = P;
         return FDTD_OK;
     }

@@ -318,7 +318,7 @@ def batch_workspace_size(instances, opts: BatchOpts | None = None) -> int:
     return int(n.value)
 
 
-def autotune(instances, probe_rows: int = 256, device: str = "cuda:0", workspace=None):
+def autotune(instances, probe_rows: int = 1024, device: str = "cuda:0", workspace=None):
     """Run the library's autotuner on this batch; returns (BatchOpts, cell updates/s of the winner)."""
     import torch
     lib = load()
