@@ -165,6 +165,19 @@ def test_decomposition_of_the_large_workload():
     assert small["cone_mode"] == 0 and small["Gs"] == 1
 
 
+def test_streaming_ring_stores_follow_the_reuse_distance():
+    """rows leave as streaming stores only when the grid writes more than the
+    256 MB last-level cache between a row's store and its re-read D rows later"""
+    llc = 256 * 2**20
+    cases = [W.large_gauss(), W.small_gauss(), *W.paper_sets().values()]
+    seen = set()
+    for inst in cases:
+        want = int(inst.D * (inst.Nx + 1) * 16 > llc)
+        assert fdtd.describe(inst)["stream_stores"] == want, inst.name
+        seen.add(want)
+    assert seen == {0, 1}
+
+
 def test_strerror_texts():
     lib = fdtd.load()
     assert lib.fdtd_strerror(0) == b"ok"
