@@ -217,10 +217,13 @@ int fdtd_sync(fdtd_ctx *ctx);
 /* Free the context (not the workspace).  Accepts NULL. */
 int fdtd_destroy(fdtd_ctx *ctx);
 
-/* Text description of the work decomposition the library would use for
- * these parameters (rows per launch, halo, workgroups of the strip and of
- * the outgoing region, ring rows), written into buf (at most n bytes,
- * NUL-terminated).  Host only; no device work. */
+/* Text description (a JSON object) of the work decomposition the library
+ * would use for these parameters (rows per launch, halo, workgroups of the
+ * strip and of the outgoing region, ring rows, and whether ring rows leave
+ * as streaming stores: stream_stores = 1 when D (Nx + 1) 16 bytes, what the
+ * grid writes between a row's store and its re-read, exceed the 256 MB
+ * last-level cache), written into buf (at most n bytes, NUL-terminated).
+ * Host only; no device work. */
 int fdtd_describe(const fdtd_params *p, char *buf, size_t n);
 
 /* Measurement aid, not part of the method: copy `bytes` (a multiple of 16,
