@@ -149,7 +149,7 @@ def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
     t0 = time.perf_counter()
     best, rate = fdtd.autotune(insts, probe_rows=1024, workspace=ws)
     t_tune = time.perf_counter() - t0
-    print(f"[bench] batch autotune: tmax={best.tmax} wmax={best.wmax} probe rate {rate:.3g} cells/s "
+    print(f"[bench] batch autotune: tmax={best.tmax} wmax={best.wmax} groups={best.groups} probe rate {rate:.3g} cells/s "
           f"({t_tune:.1f} s)", file=sys.stderr, flush=True)
     bat = fdtd.Batch(insts, best, workspace=ws)
     stream = torch.cuda.current_stream(dev)
@@ -196,7 +196,7 @@ def run_batch(n: int, seed: int, steps: int, warmup: int) -> dict:
             "instances_per_s": n / sec, "march_ms": tm / steps, "boundary_ms": tb / steps,
             "march_cell_updates_per_s": cells / (tm / steps * 1e-3), "launches": info["launches"],
             "max_workgroups_per_launch": info["max_workgroups"],
-            "autotune": {"tmax": best.tmax, "wmax": best.wmax, "graph": bool(best.use_graph),
+            "autotune": {"tmax": best.tmax, "wmax": best.wmax, "groups": best.groups, "graph": bool(best.use_graph),
                          "probe_rate": rate, "seconds": t_tune},
             "ring_GB": sum((i.D + 2 * best.tmax + 2) * (i.Nx + 1) * 16 for i in insts) / 1e9}
 

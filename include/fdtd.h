@@ -285,11 +285,13 @@ typedef struct fdtd_batch_opts {
     int32_t tmax;           /* largest block of rows per launch, 1..32 (0: 32) */
     int64_t wmax;           /* widest column range of one workgroup (0: the most one holds, 1536) */
     int32_t use_graph;      /* 1: capture the launch sequence in a HIP graph and replay it; 0: plain launches */
-    int32_t reserved;       /* must be 0 */
+    int32_t groups;         /* 0 or 1: one launch sequence; 2: the instances dealt alternately (by launch count)
+                               to two groups, each its own launch sequence (and graph) on its own stream, the
+                               second a private stream forked from and joined back into the batch's stream */
 } fdtd_batch_opts;
 
 /* Device workspace for the batch p[0..n-1] with these options (NULL: the
- * defaults, tmax 32, widest workgroups, graph on).  Batches hold one-packet
+ * defaults, tmax 32, widest workgroups, graph on, one group).  Batches hold one-packet
  * instances (identical_photons = 1) with read_mode FDTD_READ_EXACT;
  * FDTD_EINVAL otherwise. */
 int fdtd_batch_workspace_size(const fdtd_params *p, int32_t n, const fdtd_batch_opts *opts, size_t *bytes);
@@ -337,7 +339,7 @@ int fdtd_batch_sync(fdtd_batch *b);      /* FDTD_ERANGE if any instance's march 
 int fdtd_batch_destroy(fdtd_batch *b);   /* frees host state and the graph, not the workspace; accepts NULL */
 const char *fdtd_batch_last_error(const fdtd_batch *b);
 
-/* Autotuner: try each candidate (tmax in {32, 16, 8}, wmax in {1536, 768})
+/* Autotuner: try each candidate (tmax in {32, 16, 8}, wmax in {1536, 768}, groups in {1, 2})
  * whose workspace fits in `bytes`, march the first probe_rows rows of every
  * instance with plain launches, time them with HIP events on the stream, and
  * return the fastest candidate in *best (graph on) and its cell updates per

@@ -2,8 +2,11 @@
 // grid (Nx, D, Delta) and packet, advanced together.  Launch k of the batch
 // runs launch k of every instance that still needs one (block_rows), so one
 // kernel launch carries hundreds of instances; the whole launch sequence is
-// captured once in a HIP graph and replayed.  The autotuner below picks the
-// row-block cap and the workgroup width by timing a prefix of the march.
+// captured once in a HIP graph and replayed.  The instances can be dealt to
+// two groups marched concurrently on two streams, each its own launch
+// sequence and graph, so that one group's launches fill the tail of the
+// other's.  The autotuner below picks the row-block cap, the workgroup width
+// and the number of groups by timing a prefix of the march.
 
 #include <stdarg.h>
 #include <stdio.h>
@@ -19,23 +22,30 @@ struct fdtd_batch {
     int n = 0;
     std::vector<fdtd_ctx*> c;        // per instance, in the caller's order
     std::vector<int> order;          // instance ids, most launches first
-    std::vector<BInst> h_tab;        // device table contents (sorted order)
+    int G = 1;                       // groups marched concurrently (1 or 2)
+    std::vector<int> grp;            // per instance: its group
+    int gbeg[3] = {0, 0, 0};         // group g holds table entries gbeg[g] .. gbeg[g+1]-1
+    std::vector<BInst> h_tab;        // device table contents (by group, each sorted by launches)
     BInst* d_tab = nullptr;          // in the workspace
     OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
     int n_ode = 0;
     OdeTab* d_otab = nullptr;        // every instance's delay-equation step weights
     int* d_stat = nullptr;           // every instance's status word, gathered for one copy
-    ChiJob* d_jobs = nullptr;        // chi snapshots, sorted by the launch after which they are taken
+    ChiJob* d_jobs = nullptr;        // chi snapshots, by group, sorted by the launch after which they are taken
     int* d_status = nullptr;         // the batch's status word (non-finite values in any instance's march)
-    std::vector<int> job_begin;      // per launch k: first job, and one past the last (job_begin[k+1])
+    std::vector<int> job_begin[2];   // per group and launch k: first job, one past the last at k+1
+    int job_off[2] = {0, 0};         // the group's first job in d_jobs
     int64_t chi_ntau = 0;
-    std::vector<int> n_active;       // per launch k: instances still marching
-    std::vector<int> nb;             // per launch k: workgroups launched (multiple of 8)
-    int64_t Lmax = 0;
-    hipStream_t stream = nullptr;    // the caller's stream
-    hipStream_t cap = nullptr;       // private stream the graph is captured on
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<int> n_active[2];    // per group and launch k: instances still marching
+    std::vector<int> nb[2];          // per group and launch k: workgroups launched (multiple of 8)
+    int64_t L[2] = {0, 0};           // launches of each group
+    int64_t Lmax = 0;                // launches of the longest group
+    hipStream_t stream = nullptr;    // the caller's stream (group 0)
+    hipStream_t side = nullptr;      // private stream of group 1 (default priority)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t cap[2] = {nullptr, nullptr};    // private streams the graphs are captured on
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     fdtd_batch_opts o;
     int state = 0;                   // 0: no boundary, 1: ready to march, 2: marched
     char err[512];
@@ -63,6 +73,7 @@ static int opts_check(const fdtd_batch_opts* o, fdtd_batch_opts* out, char* why,
     d.tmax = BM_TMAX;
     d.wmax = BM_CAP;
     d.use_graph = 1;
+    d.groups = 1;
     if (o) {
         if (o->struct_size != sizeof(fdtd_batch_opts)) {
             snprintf(why, n, "opts struct_size %u, expected %zu", o->struct_size, sizeof(fdtd_batch_opts));
@@ -71,9 +82,11 @@ static int opts_check(const fdtd_batch_opts* o, fdtd_batch_opts* out, char* why,
         if (o->tmax < 0 || o->tmax > BM_TMAX) { snprintf(why, n, "tmax must be 0..%d", BM_TMAX); return FDTD_EINVAL; }
         if (o->wmax < 0) { snprintf(why, n, "wmax must be >= 0"); return FDTD_EINVAL; }
         if (o->use_graph != 0 && o->use_graph != 1) { snprintf(why, n, "use_graph must be 0 or 1"); return FDTD_EINVAL; }
+        if (o->groups < 0 || o->groups > 2) { snprintf(why, n, "groups must be 0, 1 or 2"); return FDTD_EINVAL; }
         if (o->tmax) d.tmax = o->tmax;
         if (o->wmax) d.wmax = o->wmax < BM_CAP ? o->wmax : BM_CAP;
         d.use_graph = o->use_graph;
+        if (o->groups) d.groups = o->groups;
     }
     *out = d;
     return FDTD_OK;
@@ -121,37 +134,70 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
 static void destroy(fdtd_batch* b)
 {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int g = 0; g < 2; ++g) {
+        if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+        if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+        if (b->cap[g]) (void)hipStreamDestroy(b->cap[g]);
+    }
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (fdtd_ctx* c : b->c) fdtd_destroy(c);
     delete b;
 }
 
-// the launches of the batch from launch k0 to k1-1 on stream s, each
-// followed by the chi snapshots whose row it completes; a march that reaches
-// the last launch ends with the non-finite check of every instance
-static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
+// launches k0 .. k1-1 of group g on stream s, each followed by the chi
+// snapshots whose row it completes; a march that reaches the group's last
+// launch ends with the non-finite check of its instances
+static int enqueue_group(fdtd_batch* b, int g, int64_t k0, int64_t k1, hipStream_t s)
 {
-    for (int64_t k = k0; k < k1 && k < b->Lmax; ++k) {
-        int rc = launch_block_batch(b->d_tab, b->n_active[k], k, b->nb[k], s);
+    const BInst* tab = b->d_tab + b->gbeg[g];
+    for (int64_t k = k0; k < k1 && k < b->L[g]; ++k) {
+        int rc = launch_block_batch(tab, b->n_active[g][k], k, b->nb[g][k], s);
         if (rc) return rc;
-        if (!b->job_begin.empty()) {
-            const int j0 = b->job_begin[k], j1 = b->job_begin[k + 1];
-            rc = launch_chi_batch(b->d_jobs + j0, j1 - j0, b->chi_ntau, s);
+        if (!b->job_begin[g].empty()) {
+            const int j0 = b->job_begin[g][k], j1 = b->job_begin[g][k + 1];
+            rc = launch_chi_batch(b->d_jobs + b->job_off[g] + j0, j1 - j0, b->chi_ntau, s);
             if (rc) return rc;
         }
     }
-    if (k1 >= b->Lmax) return launch_check_batch(b->d_tab, b->n, b->d_status, s);
+    if (k1 >= b->L[g]) return launch_check_batch(tab, b->gbeg[g + 1] - b->gbeg[g], b->d_status, s);
     return FDTD_OK;
+}
+
+// group 1 on the private stream, forked from s and joined back into it
+static int fork_side(fdtd_batch* b, hipStream_t s)
+{
+    if (hipEventRecord(b->ev_fork, s) != hipSuccess) return FDTD_EDEVICE;
+    return hipStreamWaitEvent(b->side, b->ev_fork, 0) == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+static int join_side(fdtd_batch* b, hipStream_t s)
+{
+    if (hipEventRecord(b->ev_join, b->side) != hipSuccess) return FDTD_EDEVICE;
+    return hipStreamWaitEvent(s, b->ev_join, 0) == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+}
+
+// launches k0 .. k1-1 of every group, plain launches
+static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
+{
+    if (b->G == 1) return enqueue_group(b, 0, k0, k1, s);
+    int rc = fork_side(b, s);
+    if (rc) return rc;
+    rc = enqueue_group(b, 1, k0, k1, b->side);
+    if (!rc) rc = enqueue_group(b, 0, k0, k1, s);
+    const int rj = join_side(b, s);
+    return rc ? rc : rj;
 }
 
 static void drop_graph(fdtd_batch* b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (int g = 0; g < 2; ++g) {
+        if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
+        if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
+        b->exec[g] = nullptr;
+        b->graph[g] = nullptr;
+    }
 }
 
 extern "C" {
@@ -230,35 +276,61 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
         b->order.push_back(i);
     }
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return L[x] > L[y]; });
-    b->Lmax = L[b->order[0]];
-    int64_t wg = 0;
-    std::vector<int64_t> wg_end(n);
-    for (int q = 0; q < n; ++q) {
-        const fdtd_ctx* c = b->c[b->order[q]];
-        BInst e;
-        memset(&e, 0, sizeof e);
-        e.g = c->g;
-        e.b = c->b;
-        e.P = c->plan;
-        e.wg_begin = wg;
-        e.launches = L[b->order[q]];
-        e.index = b->order[q];
-        wg += c->plan.nwg;
-        wg_end[q] = wg;
-        b->h_tab.push_back(e);
-    }
-    b->n_active.resize(b->Lmax);
-    b->nb.resize(b->Lmax);
-    int q = n;
-    for (int64_t k = 0; k < b->Lmax; ++k) {
-        while (q > 0 && b->h_tab[q - 1].launches <= k) --q;
-        b->n_active[k] = q;
-        const int64_t w = wg_end[q - 1];
-        if (w > (int64_t)0x7fffffff - 8) {
-            destroy(b);
-            return bfail(nullptr, FDTD_EINVAL, "too many workgroups in one launch");
+    // groups: instance q of that order goes to group q mod G, so each group
+    // stays sorted and the groups carry alike work
+    b->G = o.groups < n ? o.groups : n;
+    b->grp.assign(n, 0);
+    std::vector<int> tab_order;
+    for (int g = 0; g < b->G; ++g) {
+        b->gbeg[g] = (int)tab_order.size();
+        for (int q = g; q < n; q += b->G) {
+            tab_order.push_back(b->order[q]);
+            b->grp[b->order[q]] = g;
         }
-        b->nb[k] = (int)(((w + 7) / 8) * 8);
+    }
+    b->gbeg[b->G] = n;
+    for (int g = 0; g < b->G; ++g) {
+        const int q0 = b->gbeg[g], q1 = b->gbeg[g + 1];
+        int64_t wg = 0;
+        std::vector<int64_t> wg_end;
+        for (int q = q0; q < q1; ++q) {
+            const fdtd_ctx* c = b->c[tab_order[q]];
+            BInst e;
+            memset(&e, 0, sizeof e);
+            e.g = c->g;
+            e.b = c->b;
+            e.P = c->plan;
+            e.wg_begin = wg;
+            e.launches = L[tab_order[q]];
+            e.index = tab_order[q];
+            wg += c->plan.nwg;
+            wg_end.push_back(wg);
+            b->h_tab.push_back(e);
+        }
+        b->L[g] = b->h_tab[q0].launches;
+        b->n_active[g].resize(b->L[g]);
+        b->nb[g].resize(b->L[g]);
+        int q = q1 - q0;
+        for (int64_t k = 0; k < b->L[g]; ++k) {
+            while (q > 0 && b->h_tab[q0 + q - 1].launches <= k) --q;
+            b->n_active[g][k] = q;
+            const int64_t w = wg_end[q - 1];
+            if (w > (int64_t)0x7fffffff - 8) {
+                destroy(b);
+                return bfail(nullptr, FDTD_EINVAL, "too many workgroups in one launch");
+            }
+            b->nb[g][k] = (int)(((w + 7) / 8) * 8);
+        }
+    }
+    b->Lmax = b->L[0];
+    if (b->G == 2) {
+        hipError_t he = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+        if (he != hipSuccess) {
+            destroy(b);
+            return bfail(nullptr, FDTD_EDEVICE, "stream or event creation failed: %s", hipGetErrorString(he));
+        }
     }
     // delay-equation boundaries: one workgroup each in one launch, longest first
     std::vector<OdeInst> ode;
@@ -328,21 +400,26 @@ int fdtd_batch_march(fdtd_batch* b)
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     if (b->state != 1) return bfail(b, FDTD_ESTATE, "march needs a fresh boundary (fdtd_batch_set_boundary)");
     if (b->o.use_graph) {
-        if (!b->exec) {
-            hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        for (int g = 0; g < b->G; ++g) {
+            if (b->exec[g]) continue;
+            hipError_t e = b->cap[g] ? hipSuccess : hipStreamCreateWithFlags(&b->cap[g], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipStreamBeginCapture(b->cap[g], hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-            int rc = enqueue(b, 0, b->Lmax, b->cap);
-            e = hipStreamEndCapture(b->cap, &b->graph);
+            int rc = enqueue_group(b, g, 0, b->L[g], b->cap[g]);
+            e = hipStreamEndCapture(b->cap[g], &b->graph[g]);
             if (rc || e != hipSuccess)
                 return bfail(b, FDTD_EDEVICE, "graph capture failed: %s", hipGetErrorString(hipGetLastError()));
-            e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&b->exec[g], b->graph[g], nullptr, nullptr, 0);
             if (e != hipSuccess) {
-                b->exec = nullptr;
+                b->exec[g] = nullptr;
                 return bfail(b, FDTD_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
             }
         }
-        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        int rc = b->G == 2 ? fork_side(b, b->stream) : FDTD_OK;
+        hipError_t e = rc ? hipErrorLaunchFailure : hipSuccess;
+        if (e == hipSuccess && b->G == 2) e = hipGraphLaunch(b->exec[1], b->side);
+        if (e == hipSuccess) e = hipGraphLaunch(b->exec[0], b->stream);
+        if (b->G == 2 && join_side(b, b->stream) && e == hipSuccess) e = hipErrorLaunchFailure;
         if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
     } else {
         int rc = enqueue(b, 0, b->Lmax, b->stream);
@@ -370,12 +447,14 @@ int fdtd_batch_set_chi(fdtd_batch* b, const int64_t* rows, const int64_t* stride
 {
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     drop_graph(b);
-    b->job_begin.clear();
+    b->job_begin[0].clear();
+    b->job_begin[1].clear();
     b->chi_ntau = 0;
     if (!rows) return FDTD_OK;                        // snapshots off
     if (!strides || n_tau < 1 || !d_out) return bfail(b, FDTD_EINVAL, "strides, n_tau >= 1 and d_out are required");
     std::vector<ChiJob> jobs;
     std::vector<int64_t> kstar;
+    std::vector<int> jg;
     for (int i = 0; i < b->n; ++i) {
         const fdtd_ctx* c = b->c[i];
         if (rows[i] < 0) continue;
@@ -394,15 +473,25 @@ int fdtd_batch_set_chi(fdtd_batch* b, const int64_t* rows, const int64_t* stride
         jobs.push_back(j);
         // the first launch after which row `row` is complete in every column
         kstar.push_back(rows[i] == 0 ? 0 : (rows[i] + c->plan.T - 1) / c->plan.T);
+        jg.push_back(b->grp[i]);
     }
+    // by group, then by the launch after which the snapshot is taken
     std::vector<int> idx(jobs.size());
     for (size_t q = 0; q < idx.size(); ++q) idx[q] = (int)q;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return kstar[x] < kstar[y]; });
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        return jg[x] != jg[y] ? jg[x] < jg[y] : kstar[x] < kstar[y];
+    });
     std::vector<ChiJob> sorted;
     for (int q : idx) sorted.push_back(jobs[q]);
-    b->job_begin.assign(b->Lmax + 1, 0);
-    for (int q : idx) b->job_begin[kstar[q] + 1]++;
-    for (int64_t k = 0; k < b->Lmax; ++k) b->job_begin[k + 1] += b->job_begin[k];
+    int off = 0;
+    for (int g = 0; g < b->G; ++g) {
+        b->job_off[g] = off;
+        b->job_begin[g].assign(b->L[g] + 1, 0);
+        for (int q : idx)
+            if (jg[q] == g) b->job_begin[g][kstar[q] + 1]++;
+        for (int64_t k = 0; k < b->L[g]; ++k) b->job_begin[g][k + 1] += b->job_begin[g][k];
+        off += b->job_begin[g][b->L[g]];
+    }
     b->chi_ntau = n_tau;
     if (!sorted.empty()) {
         hipError_t e = hipMemcpyAsync(b->d_jobs, sorted.data(), sorted.size() * sizeof(ChiJob),
@@ -426,7 +515,11 @@ int fdtd_batch_info(const fdtd_batch* b, int64_t* launches, int64_t* max_workgro
 {
     if (!b) return FDTD_EINVAL;
     if (launches) *launches = b->Lmax;
-    if (max_workgroups) *max_workgroups = b->nb.empty() ? 0 : b->nb[0];
+    if (max_workgroups) {
+        int64_t w = 0;
+        for (int g = 0; g < b->G; ++g) w += b->nb[g].empty() ? 0 : b->nb[g][0];
+        *max_workgroups = w;
+    }
     return FDTD_OK;
 }
 
@@ -451,16 +544,17 @@ int fdtd_batch_destroy(fdtd_batch* b)
 
 const char* fdtd_batch_last_error(const fdtd_batch* b) { return b ? b->err : g_berr; }
 
-// Autotuner: for each candidate (row-block cap, workgroup width cap) that
-// fits the workspace, set up the batch, march its first probe_rows rows with
-// plain launches and time them with events; the candidate with the most cell
-// updates per second wins (graph capture is switched on in the result).
+// Autotuner: for each candidate (row-block cap, workgroup width cap, groups)
+// that fits the workspace, set up the batch, march its first probe_rows rows
+// with plain launches and time them with events; the candidate with the most
+// cell updates per second wins (graph capture is switched on in the result).
 int fdtd_batch_autotune(const fdtd_params* p, int32_t n, void* d_workspace, size_t bytes, void* hip_stream,
                         int64_t probe_rows, fdtd_batch_opts* best, double* best_rate)
 {
     if (!p || n < 1 || !best || probe_rows < 1) return bfail(nullptr, FDTD_EINVAL, "bad arguments");
     static const int tmaxes[] = {32, 16, 8};
     static const int64_t wmaxes[] = {BM_CAP, 768};
+    static const int groupss[] = {1, 2};
     double top = -1.0;
     fdtd_batch_opts win;
     memset(&win, 0, sizeof win);
@@ -471,12 +565,14 @@ int fdtd_batch_autotune(const fdtd_params* p, int32_t n, void* d_workspace, size
     int rc = FDTD_OK;
     for (int tm : tmaxes) {
         for (int64_t wm : wmaxes) {
+          for (int gr : groupss) {
             fdtd_batch_opts o;
             memset(&o, 0, sizeof o);
             o.struct_size = sizeof o;
             o.tmax = tm;
             o.wmax = wm;
             o.use_graph = 0;
+            o.groups = gr;
             size_t need = 0;
             if (fdtd_batch_workspace_size(p, n, &o, &need) != FDTD_OK || need > bytes) continue;
             fdtd_batch* b = nullptr;
@@ -514,6 +610,8 @@ int fdtd_batch_autotune(const fdtd_params* p, int32_t n, void* d_workspace, size
                 top = rate;
                 win = o;
             }
+          }
+          if (rc) break;
         }
         if (rc) break;
     }

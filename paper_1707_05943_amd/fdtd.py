@@ -51,12 +51,12 @@ class FdtdParams(ctypes.Structure):
 
 class BatchOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("tmax", ctypes.c_int32), ("wmax", ctypes.c_int64),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("groups", ctypes.c_int32)]
 
 
-def batch_opts(tmax: int = 0, wmax: int = 0, use_graph: bool = True) -> BatchOpts:
+def batch_opts(tmax: int = 0, wmax: int = 0, use_graph: bool = True, groups: int = 1) -> BatchOpts:
     return BatchOpts(struct_size=ctypes.sizeof(BatchOpts), tmax=int(tmax), wmax=int(wmax),
-                     use_graph=1 if use_graph else 0, reserved=0)
+                     use_graph=1 if use_graph else 0, groups=int(groups))
 
 
 class FdtdError(RuntimeError):

@@ -90,16 +90,53 @@ def oracle_runs():
     return cases, [_oracle(inst) for inst in cases]
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_vs_oracle(oracle_runs, use_graph):
+@pytest.mark.parametrize("use_graph,groups", [(False, 1), (True, 1), (False, 2), (True, 2)])
+def test_batch_vs_oracle(oracle_runs, use_graph, groups):
     cases, refs = oracle_runs
-    _say(f"[batch] {len(cases)} instances, graph={use_graph}")
-    bat = fdtd.Batch(cases, fdtd.batch_opts(use_graph=use_graph)).set_boundary().march()
+    _say(f"[batch] {len(cases)} instances, graph={use_graph}, groups={groups}")
+    bat = fdtd.Batch(cases, fdtd.batch_opts(use_graph=use_graph, groups=groups)).set_boundary().march()
     _say(f"[batch] launches {bat.info()}")
     for i, inst in enumerate(cases):
-        w = _compare_instance(bat, i, inst, refs[i], f"graph={use_graph}")
+        w = _compare_instance(bat, i, inst, refs[i], f"graph={use_graph} groups={groups}")
         _say(f"[batch] {inst.name}: worst {w:.2e}")
     bat.close()
+
+
+def test_two_groups_match_one_group():
+    """two groups on two streams run the same kernels on the same instances:
+    rows, P_e and the chi snapshots (taken per group) are bitwise those of one
+    group, over graph replays with other device work in between"""
+    import torch
+    cases = batch_cases()
+    n_tau = 24
+    rows = [max(1, inst.Nt // 2) for inst in cases]
+    rows[1] = -1
+    strides = [1 + (i % 2) for i in range(len(cases))]
+
+    def run(groups, reps):
+        out = torch.zeros(len(cases), n_tau, dtype=torch.complex128, device="cuda:0")
+        bat = fdtd.Batch(cases, fdtd.batch_opts(use_graph=True, groups=groups))
+        bat.set_chi(rows, strides, n_tau, out)
+        res = []
+        x = torch.ones(1 << 18, dtype=torch.float64, device="cuda:0")
+        for rep in range(reps):
+            _say(f"[batch] groups={groups} replay {rep}")
+            bat.set_boundary().march()
+            x = x * 1.0001 + 1.0
+            torch.cuda.synchronize()
+            res.append(([bat.pe(i) for i in range(len(cases))],
+                        [bat.row_values(i, cases[i].Nt) for i in range(len(cases))], out.cpu().numpy().copy()))
+        _say(f"[batch] groups={groups}: launches, workgroups {bat.info()}")
+        bat.close()
+        return res
+
+    want = run(1, 1)[0]
+    for rep, got in enumerate(run(2, 3)):
+        for i in range(len(cases)):
+            assert np.array_equal(got[0][i], want[0][i]), (rep, i, "P_e")
+            assert np.array_equal(got[1][i], want[1][i]), (rep, i, "row")
+        assert np.array_equal(got[2], want[2]), (rep, "chi")
+    assert np.abs(want[2]).max() > 0
 
 
 def test_graph_replays_match_plain_launches():
