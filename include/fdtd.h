@@ -285,9 +285,9 @@ typedef struct fdtd_batch_opts {
     int32_t tmax;           /* largest block of rows per launch, 1..32 (0: 32) */
     int64_t wmax;           /* widest column range of one workgroup (0: the most one holds, 1536) */
     int32_t use_graph;      /* 1: capture the launch sequence in a HIP graph and replay it; 0: plain launches */
-    int32_t groups;         /* 0 or 1: one launch sequence; 2: the instances dealt alternately (by launch count)
-                               to two groups, each its own launch sequence (and graph) on its own stream, the
-                               second a private stream forked from and joined back into the batch's stream */
+    int32_t groups;         /* 0 or 1: one launch sequence; 2..4: the instances dealt in turn (by launch count)
+                               to that many groups, each its own launch sequence (and graph) on its own stream,
+                               the others private streams forked from and joined back into the batch's stream */
 } fdtd_batch_opts;
 
 /* Device workspace for the batch p[0..n-1] with these options (NULL: the

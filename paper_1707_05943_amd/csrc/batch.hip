@@ -3,9 +3,9 @@
 // runs launch k of every instance that still needs one (block_rows), so one
 // kernel launch carries hundreds of instances; the whole launch sequence is
 // captured once in a HIP graph and replayed.  The instances can be dealt to
-// two groups marched concurrently on two streams, each its own launch
-// sequence and graph, so that one group's launches fill the tail of the
-// other's.  The autotuner below picks the row-block cap, the workgroup width
+// up to MAXG groups marched concurrently on their own streams, each its own
+// launch sequence and graph, so that one group's launches fill the tails of
+// the others'.  The autotuner below picks the row-block cap, the workgroup width
 // and the number of groups by timing a prefix of the march.
 
 #include <stdarg.h>
@@ -18,13 +18,15 @@
 
 #include "fdtd_common.h"
 
+constexpr int MAXG = 4;              // concurrently marched groups (streams) at most
+
 struct fdtd_batch {
     int n = 0;
     std::vector<fdtd_ctx*> c;        // per instance, in the caller's order
     std::vector<int> order;          // instance ids, most launches first
-    int G = 1;                       // groups marched concurrently (1 or 2)
+    int G = 1;                       // groups marched concurrently (1 .. MAXG)
     std::vector<int> grp;            // per instance: its group
-    int gbeg[3] = {0, 0, 0};         // group g holds table entries gbeg[g] .. gbeg[g+1]-1
+    int gbeg[MAXG + 1] = {};         // group g holds table entries gbeg[g] .. gbeg[g+1]-1
     std::vector<BInst> h_tab;        // device table contents (by group, each sorted by launches)
     BInst* d_tab = nullptr;          // in the workspace
     OdeInst* d_ode = nullptr;        // delay-equation boundary records of those instances that use it
@@ -33,19 +35,20 @@ struct fdtd_batch {
     int* d_stat = nullptr;           // every instance's status word, gathered for one copy
     ChiJob* d_jobs = nullptr;        // chi snapshots, by group, sorted by the launch after which they are taken
     int* d_status = nullptr;         // the batch's status word (non-finite values in any instance's march)
-    std::vector<int> job_begin[2];   // per group and launch k: first job, one past the last at k+1
-    int job_off[2] = {0, 0};         // the group's first job in d_jobs
+    std::vector<int> job_begin[MAXG];    // per group and launch k: first job, one past the last at k+1
+    int job_off[MAXG] = {};          // the group's first job in d_jobs
     int64_t chi_ntau = 0;
-    std::vector<int> n_active[2];    // per group and launch k: instances still marching
-    std::vector<int> nb[2];          // per group and launch k: workgroups launched (multiple of 8)
-    int64_t L[2] = {0, 0};           // launches of each group
+    std::vector<int> n_active[MAXG];     // per group and launch k: instances still marching
+    std::vector<int> nb[MAXG];       // per group and launch k: workgroups launched (multiple of 8)
+    int64_t L[MAXG] = {};            // launches of each group
     int64_t Lmax = 0;                // launches of the longest group
     hipStream_t stream = nullptr;    // the caller's stream (group 0)
-    hipStream_t side = nullptr;      // private stream of group 1 (default priority)
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipStream_t cap[2] = {nullptr, nullptr};    // private streams the graphs are captured on
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipStream_t side[MAXG] = {};     // private streams of groups 1 .. G-1 (default priority)
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[MAXG] = {};
+    hipStream_t cap[MAXG] = {};      // private streams the graphs are captured on
+    hipGraph_t graph[MAXG] = {};
+    hipGraphExec_t exec[MAXG] = {};
     fdtd_batch_opts o;
     int state = 0;                   // 0: no boundary, 1: ready to march, 2: marched
     char err[512];
@@ -82,7 +85,7 @@ static int opts_check(const fdtd_batch_opts* o, fdtd_batch_opts* out, char* why,
         if (o->tmax < 0 || o->tmax > BM_TMAX) { snprintf(why, n, "tmax must be 0..%d", BM_TMAX); return FDTD_EINVAL; }
         if (o->wmax < 0) { snprintf(why, n, "wmax must be >= 0"); return FDTD_EINVAL; }
         if (o->use_graph != 0 && o->use_graph != 1) { snprintf(why, n, "use_graph must be 0 or 1"); return FDTD_EINVAL; }
-        if (o->groups < 0 || o->groups > 2) { snprintf(why, n, "groups must be 0, 1 or 2"); return FDTD_EINVAL; }
+        if (o->groups < 0 || o->groups > MAXG) { snprintf(why, n, "groups must be 0..%d", MAXG); return FDTD_EINVAL; }
         if (o->tmax) d.tmax = o->tmax;
         if (o->wmax) d.wmax = o->wmax < BM_CAP ? o->wmax : BM_CAP;
         d.use_graph = o->use_graph;
@@ -134,14 +137,14 @@ static int batch_bytes(const fdtd_params* p, int32_t n, const fdtd_batch_opts& o
 static void destroy(fdtd_batch* b)
 {
     if (!b) return;
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < MAXG; ++g) {
         if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
         if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
         if (b->cap[g]) (void)hipStreamDestroy(b->cap[g]);
+        if (b->side[g]) (void)hipStreamDestroy(b->side[g]);
+        if (b->ev_join[g]) (void)hipEventDestroy(b->ev_join[g]);
     }
-    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (fdtd_ctx* c : b->c) fdtd_destroy(c);
     delete b;
 }
@@ -165,26 +168,33 @@ static int enqueue_group(fdtd_batch* b, int g, int64_t k0, int64_t k1, hipStream
     return FDTD_OK;
 }
 
-// group 1 on the private stream, forked from s and joined back into it
+// groups 1 .. G-1 on their private streams, forked from s and joined back into it
 static int fork_side(fdtd_batch* b, hipStream_t s)
 {
+    if (b->G == 1) return FDTD_OK;
     if (hipEventRecord(b->ev_fork, s) != hipSuccess) return FDTD_EDEVICE;
-    return hipStreamWaitEvent(b->side, b->ev_fork, 0) == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+    for (int g = 1; g < b->G; ++g)
+        if (hipStreamWaitEvent(b->side[g], b->ev_fork, 0) != hipSuccess) return FDTD_EDEVICE;
+    return FDTD_OK;
 }
 
 static int join_side(fdtd_batch* b, hipStream_t s)
 {
-    if (hipEventRecord(b->ev_join, b->side) != hipSuccess) return FDTD_EDEVICE;
-    return hipStreamWaitEvent(s, b->ev_join, 0) == hipSuccess ? FDTD_OK : FDTD_EDEVICE;
+    int rc = FDTD_OK;
+    for (int g = 1; g < b->G; ++g) {
+        if (hipEventRecord(b->ev_join[g], b->side[g]) != hipSuccess ||
+            hipStreamWaitEvent(s, b->ev_join[g], 0) != hipSuccess)
+            rc = FDTD_EDEVICE;
+    }
+    return rc;
 }
 
 // launches k0 .. k1-1 of every group, plain launches
 static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
 {
-    if (b->G == 1) return enqueue_group(b, 0, k0, k1, s);
     int rc = fork_side(b, s);
     if (rc) return rc;
-    rc = enqueue_group(b, 1, k0, k1, b->side);
+    for (int g = b->G - 1; g >= 1 && !rc; --g) rc = enqueue_group(b, g, k0, k1, b->side[g]);
     if (!rc) rc = enqueue_group(b, 0, k0, k1, s);
     const int rj = join_side(b, s);
     return rc ? rc : rj;
@@ -192,7 +202,7 @@ static int enqueue(fdtd_batch* b, int64_t k0, int64_t k1, hipStream_t s)
 
 static void drop_graph(fdtd_batch* b)
 {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < MAXG; ++g) {
         if (b->exec[g]) (void)hipGraphExecDestroy(b->exec[g]);
         if (b->graph[g]) (void)hipGraphDestroy(b->graph[g]);
         b->exec[g] = nullptr;
@@ -323,10 +333,12 @@ int fdtd_batch_init(const fdtd_params* p, int32_t n, const fdtd_batch_opts* opts
         }
     }
     b->Lmax = b->L[0];
-    if (b->G == 2) {
-        hipError_t he = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
-        if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
-        if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
+    if (b->G > 1) {
+        hipError_t he = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        for (int g = 1; g < b->G && he == hipSuccess; ++g) {
+            he = hipStreamCreateWithFlags(&b->side[g], hipStreamNonBlocking);
+            if (he == hipSuccess) he = hipEventCreateWithFlags(&b->ev_join[g], hipEventDisableTiming);
+        }
         if (he != hipSuccess) {
             destroy(b);
             return bfail(nullptr, FDTD_EDEVICE, "stream or event creation failed: %s", hipGetErrorString(he));
@@ -415,11 +427,11 @@ int fdtd_batch_march(fdtd_batch* b)
                 return bfail(b, FDTD_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
             }
         }
-        int rc = b->G == 2 ? fork_side(b, b->stream) : FDTD_OK;
+        int rc = fork_side(b, b->stream);
         hipError_t e = rc ? hipErrorLaunchFailure : hipSuccess;
-        if (e == hipSuccess && b->G == 2) e = hipGraphLaunch(b->exec[1], b->side);
+        for (int g = b->G - 1; g >= 1 && e == hipSuccess; --g) e = hipGraphLaunch(b->exec[g], b->side[g]);
         if (e == hipSuccess) e = hipGraphLaunch(b->exec[0], b->stream);
-        if (b->G == 2 && join_side(b, b->stream) && e == hipSuccess) e = hipErrorLaunchFailure;
+        if (join_side(b, b->stream) && e == hipSuccess) e = hipErrorLaunchFailure;
         if (e != hipSuccess) return bfail(b, FDTD_EDEVICE, "graph launch failed: %s", hipGetErrorString(e));
     } else {
         int rc = enqueue(b, 0, b->Lmax, b->stream);
@@ -447,8 +459,7 @@ int fdtd_batch_set_chi(fdtd_batch* b, const int64_t* rows, const int64_t* stride
 {
     if (!b) return bfail(nullptr, FDTD_EINVAL, "batch is NULL");
     drop_graph(b);
-    b->job_begin[0].clear();
-    b->job_begin[1].clear();
+    for (int g = 0; g < MAXG; ++g) b->job_begin[g].clear();
     b->chi_ntau = 0;
     if (!rows) return FDTD_OK;                        // snapshots off
     if (!strides || n_tau < 1 || !d_out) return bfail(b, FDTD_EINVAL, "strides, n_tau >= 1 and d_out are required");

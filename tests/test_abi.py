@@ -203,9 +203,10 @@ def test_batch_workspace_and_validation():
     o.struct_size = 8
     with pytest.raises(fdtd.FdtdError):
         fdtd.batch_workspace_size(cases, o)
-    # one or two concurrent groups need the same workspace; three are refused
+    # one to four concurrent groups need the same workspace; five are refused
     assert fdtd.batch_workspace_size(cases, fdtd.batch_opts(groups=2)) == n_default
+    assert fdtd.batch_workspace_size(cases, fdtd.batch_opts(groups=4)) == n_default
     assert fdtd.batch_workspace_size(cases, fdtd.batch_opts(groups=0)) == n_default
     with pytest.raises(fdtd.FdtdError) as e:
-        fdtd.batch_workspace_size(cases, fdtd.batch_opts(groups=3))
+        fdtd.batch_workspace_size(cases, fdtd.batch_opts(groups=5))
     assert e.value.code == -1 and "groups" in str(e.value)

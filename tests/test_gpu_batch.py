@@ -102,8 +102,9 @@ def test_batch_vs_oracle(oracle_runs, use_graph, groups):
     bat.close()
 
 
-def test_two_groups_match_one_group():
-    """two groups on two streams run the same kernels on the same instances:
+@pytest.mark.parametrize("groups", [2, 4])
+def test_groups_match_one_group(groups):
+    """groups on their own streams run the same kernels on the same instances:
     rows, P_e and the chi snapshots (taken per group) are bitwise those of one
     group, over graph replays with other device work in between"""
     import torch
@@ -131,7 +132,7 @@ def test_two_groups_match_one_group():
         return res
 
     want = run(1, 1)[0]
-    for rep, got in enumerate(run(2, 3)):
+    for rep, got in enumerate(run(groups, 3)):
         for i in range(len(cases)):
             assert np.array_equal(got[0][i], want[0][i]), (rep, i, "P_e")
             assert np.array_equal(got[1][i], want[1][i]), (rep, i, "row")
