@@ -116,13 +116,15 @@ def coarse(inst, factor: int):
 
 
 class Solver:
-    """Batched FP64 solves of lists of instances, reusing one workspace."""
+    """Batched FP64 solves of lists of instances, reusing one workspace (by
+    default in two concurrently marched groups, the autotuner's pick for the
+    512-instance sweep draw)."""
 
     def __init__(self, device="cuda:0", opts=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.opts = opts if opts is not None else fdtd.batch_opts()
+        self.opts = opts if opts is not None else fdtd.batch_opts(groups=2)
         self.ws = None
 
     def _workspace(self, insts):
