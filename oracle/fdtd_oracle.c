@@ -592,8 +592,12 @@ static cplx solve_cell(orc_state *s, int64_t j, int64_t r, cplx left /* psi(j-1,
     else if (p->incident != INC_EXP1 && r - j >= 0)
         rhs += sqrt(G) * cexp(I * p->phase) * s->phig[r - j] * drive_row;
     (void)a; (void)dl;
-    /* (U - bl)/Delta + (W/4)(bl + br + tl + U) = rhs */
-    return (rhs + bl / dl - (W / 4.0) * (bl + br + tl)) / (1.0 / dl + W / 4.0);
+    /* (U - bl)/Delta + (W/4)(bl + br + tl + U) = rhs, solved for the
+     * increment U - bl: (U - bl)(1/Delta + W/4) = rhs - (W/4)(2 bl + br + tl).
+     * (Solved for U instead, the rounded divisor would scale psi once per row
+     * along every characteristic and bias the march by about one rounding per
+     * row; here it scales only the increment.) */
+    return bl + (rhs - (W / 4.0) * (2.0 * bl + br + tl)) / (1.0 / dl + W / 4.0);
 }
 
 /* chi(x1, x2, t_r) at x1 = a + Delta (column D+1), x2 = x1 + k Delta
