@@ -335,6 +335,39 @@ def test_large_gauss_column_window():
     sol.close()
 
 
+def test_large_gauss_strip_to_the_end():
+    """D=10000, Nx=262144 marched on the GPU over all 131072 rows (4097
+    launches of the benchmark's configuration, in three march calls), the
+    strip's 27 workgroups and the first near workgroup compared with the
+    oracle run on columns 0..D+400 (chirality) at rows spread over the whole
+    march, each with its block's neighbour rows and the oldest row the ring
+    holds: no drift over the long march (the field there keeps 1% of its peak
+    norm at the last row)"""
+    big = W.large_gauss()
+    win = W.with_sizes(big, Nx=big.D + 400)
+    T = fdtd.describe(big)["T"]
+    samples = [40000, 80000, big.Nt]
+    snap = sorted({x for r in samples for x in (r - big.D - 1, r - T, r - 1, r)})
+    _say(f"[parity] {big.name} to row {big.Nt}: oracle on {win.Nx + 1} columns, rows {snap}")
+    E = oracle.E_table(win)
+    ref = oracle.march(win, E, snap_rows=snap, want_ring=False)
+    want = dict(zip(snap, ref["snaps"]))
+    _say("[parity] oracle done")
+    sol = fdtd.Solver(big).set_boundary()
+    scale = max(np.linalg.norm(v) for v in want.values())
+    done = 0
+    for r in samples:
+        sol.march(r - done)
+        done = r
+        for rho in (x for x in snap if r - big.D - 1 <= x <= r):
+            got = sol.row_values(rho)[: win.Nx + 1]
+            e = _row_err(got, want[rho], scale)
+            _say(f"[parity] row {rho}: {e:.2e} (row norm {np.linalg.norm(want[rho]):.3g})")
+            assert e <= TOL, ("row", rho, e)
+    _say(f"[parity] {big.name} to the end: worst row against its own norm {_unfloored_reset():.2e}")
+    sol.close()
+
+
 @pytest.mark.parametrize("name", list(W.paper_sets()))
 def test_paper_parameter_sets_column_window(name):
     """The paper's validation parameter sets (plane wave; the error snapshots,
