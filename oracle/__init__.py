@@ -15,7 +15,9 @@ Parity status of each part (what pins it, see tests/test_oracle_*.py):
     one-excitation probability, and the plane-wave superposition
   * march (HYBRID reads)       -- the literal micro-oracle; the micro-oracle in
     turn converges to the exact solution in x <= -a (paper's test 1) and
-    conserves the two-excitation probability as Delta -> 0
+    conserves the two-excitation probability as Delta -> 0; the rounding of
+    long FP64 marches against the same source built in long double
+    (`march(..., long_double=True)`)
   * march with the paper's own reads (march_diag) -- the micro-oracle's
     paper_diag mode; second-order convergence to the exact solution in
     x <= -a (the paper's test 1) and to the hybrid march right of -a
@@ -34,16 +36,21 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fdtd_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_PATH_LD = os.path.join(_HERE, "liboracle_ld.so")
 _lib = None
+_lib_ld = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle's C source with gcc (no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                        "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB_PATH)
+    """Compile the oracle's C source with gcc (no FMA contraction, no
+    fast-math): the FP64 library, and the same source with its arithmetic in
+    long double (-DORC_LONG_DOUBLE; the arrays passed stay double)."""
+    for path, extra in ((_LIB_PATH, []), (_LIB_PATH_LD, ["-DORC_LONG_DOUBLE"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp"
+            subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", *extra,
+                            "-o", tmp, _SRC, "-lm"], check=True)
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -58,12 +65,14 @@ class OrcParams(ctypes.Structure):
                 ("alpha2", ctypes.c_double)]
 
 
-def _load():
-    global _lib
-    if _lib is not None:
+def _load(long_double: bool = False):
+    global _lib, _lib_ld
+    if long_double and _lib_ld is not None:
+        return _lib_ld
+    if not long_double and _lib is not None:
         return _lib
     build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH_LD if long_double else _LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
     i64 = ctypes.c_int64
@@ -82,7 +91,10 @@ def _load():
     lib.orc_exact_part_arr.argtypes = [P(OrcParams), vp, vp]
     lib.orc_two_photon_A.argtypes = [P(OrcParams)]
     lib.orc_two_photon_A.restype = ctypes.c_double
-    _lib = lib
+    if long_double:
+        _lib_ld = lib
+    else:
+        _lib = lib
     return lib
 
 
@@ -191,16 +203,17 @@ def E_table(inst, mode: int = 0) -> np.ndarray:
 
 
 def march(inst, E: np.ndarray | None = None, *, chi_rows=(), n_tau: int = 0, snap_rows=(),
-          want_ring: bool = True, want_pe: bool = True) -> dict:
+          want_ring: bool = True, want_pe: bool = True, long_double: bool = False) -> dict:
     """Run the oracle march over rows 1..Nt (HYBRID reads: x <= -a from the
-    exact solution).  Returns a dict with
+    exact solution); long_double: the same source with its arithmetic in
+    long double (the inputs and results are double).  Returns a dict with
       E    : the boundary table used, E(t_r)
       pe   : P_e(t_r), r = 0..Nt
       ring : rows Nt-D-1 .. Nt (oldest first), columns 0..Nx
       chi  : chi at detectors x1 = a + Delta, x2 = x1 + k Delta (k < n_tau), per chi row
       snaps: full rows at snap_rows
     """
-    lib = _load()
+    lib = _load(long_double)
     p = params(inst)
     if E is None:
         E = E_table(inst)

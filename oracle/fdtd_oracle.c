@@ -25,7 +25,15 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* The complex type of the arithmetic.  Built with -DORC_LONG_DOUBLE it is
+ * long double (an extended-precision build that pins the rounding of the
+ * FP64 march); the arrays a caller passes are double complex either way. */
+#ifdef ORC_LONG_DOUBLE
+typedef long double complex cplx;
+#else
 typedef double complex cplx;
+#endif
+typedef double complex dcplx;
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -441,7 +449,7 @@ cplx orc_E_quad(const orc_params *p, double t)
 /* The same series on the grid t_r = r Delta: with 2a = D Delta, the shifted
  * times are T = (r - nD) Delta, so J_n is needed at T = q Delta only and each
  * value serves two rows (r = q + nD and r = q + (n+1)D). */
-static void E_table_quad(const orc_params *p, cplx *E)
+static void E_table_quad(const orc_params *p, dcplx *E)
 {
     const int64_t Nt = p->Nt, D = p->D;
     const double G = p->Gamma, dl = p->Delta;
@@ -470,7 +478,7 @@ static void E_table_quad(const orc_params *p, cplx *E)
  * quadrature of the delay series.  mode 0: default, 1: force quadrature (on
  * the grid), 2: quadrature row by row.  Two different photons: e0^(1) in
  * E[0..Nt], then e0^(2) in E[Nt+1..2Nt+1]. */
-void orc_E_table(const orc_params *p, int mode, cplx *E)
+void orc_E_table(const orc_params *p, int mode, dcplx *E)
 {
     if (two_photons(p)) {
         orc_params a = photon(p, 1), b = photon(p, 2);
@@ -492,10 +500,10 @@ void orc_E_table(const orc_params *p, int mode, cplx *E)
 
 typedef struct {
     const orc_params *p;
-    const cplx *E;           /* E(t_r), r = 0..Nt (two different photons: e0^(1)) */
+    const dcplx *E;          /* E(t_r), r = 0..Nt (two different photons: e0^(1)) */
     const cplx *phig;        /* phi(-a - q Delta), q = 0..Nt: phi at the grid points x - t of x <= -a
                                 (two different photons: phi1) */
-    const cplx *E2;          /* two different photons: e0^(2)(t_r); else NULL */
+    const dcplx *E2;         /* two different photons: e0^(2)(t_r); else NULL */
     const cplx *phig2;       /* two different photons: phi2(-a - q Delta); else NULL */
     cplx c_ex;               /* psi = c_ex phi(x-t) E(t) in x <= -a (two photons: c_ex [phi1 e0^(2) + phi2 e0^(1)]) */
     cplx *ring;              /* (D+2) rows of Nx+1 columns; row rho in slot rho mod (D+2) */
@@ -699,9 +707,9 @@ static double pe_row(orc_state *s, int64_t r)
  *   snap_rows/n_snap, snaps : full rows (Nx+1 values) at the listed rows
  * Returns 0, or -1 when a read broke the lag bound (an oracle bug).
  */
-int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
-              const int64_t *chi_rows, int64_t n_chi_rows, int64_t n_tau, cplx *chi,
-              const int64_t *snap_rows, int64_t n_snap, cplx *snaps)
+int orc_march(const orc_params *p, const dcplx *E, double *pe, dcplx *ring_out,
+              const int64_t *chi_rows, int64_t n_chi_rows, int64_t n_tau, dcplx *chi,
+              const int64_t *snap_rows, int64_t n_snap, dcplx *snaps)
 {
     const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt, R = D + 2, C = Nx + 1;
     const int two = two_photons(p);
@@ -781,7 +789,7 @@ int orc_march(const orc_params *p, const cplx *E, double *pe, cplx *ring_out,
  * Returns 0, -1 when a read reached a point not yet solved, -2 when out of
  * memory.
  */
-int orc_march_diag(const orc_params *p, const cplx *E, int64_t diag_cols, double *pe,
+int orc_march_diag(const orc_params *p, const dcplx *E, int64_t diag_cols, double *pe,
                    const int64_t *snap_rows, int64_t n_snap, cplx *snaps)
 {
     const int64_t D = p->D, Nx = p->Nx, Nt = p->Nt;
@@ -836,7 +844,7 @@ double orc_phi_mass_below(const orc_params *p, double y) { return phi_mass_below
  * pointer-based entry points for the Python test harness (ctypes cannot
  * pass C99 complex values): complex arrays are interleaved (re, im) pairs
  * ====================================================================== */
-void orc_gamma_P_arr(int64_t m, const int32_t *n, const cplx *z, cplx *out, int32_t *regime, int32_t *ok)
+void orc_gamma_P_arr(int64_t m, const int32_t *n, const dcplx *z, dcplx *out, int32_t *regime, int32_t *ok)
 {
     for (int64_t i = 0; i < m; ++i) {
         out[i] = orc_gamma_P(n[i], z[i]);
@@ -845,27 +853,27 @@ void orc_gamma_P_arr(int64_t m, const int32_t *n, const cplx *z, cplx *out, int3
     }
 }
 
-void orc_gamma_P_regime_arr(int64_t m, const int32_t *n, const cplx *z, int32_t regime, cplx *out)
+void orc_gamma_P_regime_arr(int64_t m, const int32_t *n, const dcplx *z, int32_t regime, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_gamma_P_regime(n[i], z[i], regime);
 }
 
-void orc_E_closed_arr(const orc_params *p, int64_t m, const double *t, cplx *out)
+void orc_E_closed_arr(const orc_params *p, int64_t m, const double *t, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_E_closed(p, t[i]);
 }
 
-void orc_E_quad_arr(const orc_params *p, int64_t m, const double *t, cplx *out)
+void orc_E_quad_arr(const orc_params *p, int64_t m, const double *t, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_E_quad(p, t[i]);
 }
 
-void orc_Jn_quad_arr(const orc_params *p, int n, int64_t m, const double *T, cplx *out)
+void orc_Jn_quad_arr(const orc_params *p, int n, int64_t m, const double *T, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_Jn_quad(p, n, T[i]);
 }
 
-void orc_phi_arr(const orc_params *p, int64_t m, const double *x, cplx *out)
+void orc_phi_arr(const orc_params *p, int64_t m, const double *x, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_phi(p, x[i]);
 }
@@ -875,14 +883,14 @@ void orc_phi_mass_below_arr(const orc_params *p, int64_t m, const double *y, dou
     for (int64_t i = 0; i < m; ++i) out[i] = phi_mass_below(p, y[i]);
 }
 
-void orc_chi0_arr(const orc_params *p, int64_t m, const double *x1, const double *x2, cplx *out)
+void orc_chi0_arr(const orc_params *p, int64_t m, const double *x1, const double *x2, dcplx *out)
 {
     for (int64_t i = 0; i < m; ++i) out[i] = orc_chi0(p, x1[i], x2[i]);
 }
 
 /* int_{-inf}^{-a} |psi(x, t_r)|^2 dx of the exact solution for rows r = 0..Nt
  * (E as for orc_march) */
-void orc_exact_part_arr(const orc_params *p, const cplx *E, double *out)
+void orc_exact_part_arr(const orc_params *p, const dcplx *E, double *out)
 {
     const int64_t Nt = p->Nt;
     orc_state s = { p, E, NULL, NULL, NULL, 0.0, NULL, 0, 0, NULL, 0, 0 };

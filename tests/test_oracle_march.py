@@ -134,3 +134,25 @@ def test_no_growth_over_many_rows():
     res = oracle.march(inst, E, snap_rows=[200, 1200])
     assert np.abs(res["snaps"][1]).max() < 1e-3 * np.abs(res["snaps"][0]).max()
     assert np.all(np.isfinite(res["pe"]))
+
+
+def test_fp64_march_against_its_long_double_build():
+    """the rounding of a long FP64 march: the same source built with its
+    arithmetic in long double (64-bit significand) gives the march of the
+    same inputs with 2^11 times less rounding per operation.  Along a
+    characteristic the scheme does not damp rounding (|xi| = 1 at
+    k Delta = pi, App. A), so the FP64 march may drift by at most about one
+    rounding (2^-53) of the row per row; rows that have decayed are measured
+    against 1% of the peak row.  The paper's error-snapshot set (a plane wave
+    held up by its drive) on its first 400 columns over 20000 rows."""
+    inst = W.with_sizes(W.paper_sets()["paper_error_snapshots"], Nx=400, Nt=20000)
+    E = oracle.E_table(inst)
+    rows = [1000, 5000, 10000, 15000, 20000]
+    a = oracle.march(inst, E, snap_rows=rows, want_ring=False)["snaps"]
+    b = oracle.march(inst, E, snap_rows=rows, want_ring=False, long_double=True)["snaps"]
+    scale = max(np.linalg.norm(v) for v in b)
+    errs = [np.linalg.norm(x - y) / max(np.linalg.norm(y), 0.01 * scale) for x, y in zip(a, b)]
+    assert max(errs) > 0.0                                # two builds, two roundings
+    assert min(np.linalg.norm(v) for v in b) > 0.1 * scale  # the field is held up, not decayed
+    for r, e in zip(rows, errs):
+        assert e <= r * 2.0**-53, (r, e)
