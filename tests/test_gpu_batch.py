@@ -327,3 +327,17 @@ def test_sweep_draw_instances_in_the_full_batch():
     bat.close()
     del ws
     torch.cuda.empty_cache()
+
+
+def test_one_instance_batch_with_more_groups_than_instances():
+    """a batch of one instance asked for four groups marches as one group and
+    gives bitwise the single-group batch"""
+    inst = batch_cases()[0]
+    one = fdtd.Batch([inst], fdtd.batch_opts(groups=1)).set_boundary().march()
+    four = fdtd.Batch([inst], fdtd.batch_opts(groups=4)).set_boundary().march()
+    assert four.info() == one.info()
+    assert np.array_equal(four.pe(0), one.pe(0))
+    assert np.array_equal(four.row_values(0, inst.Nt), one.row_values(0, inst.Nt))
+    one.close()
+    four.close()
+

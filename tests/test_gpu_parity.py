@@ -556,3 +556,27 @@ def test_state_errors():
     with pytest.raises(fdtd.FdtdError) as e:
         sol.row_values(inst.Nt - inst.D - 2)   # no longer in the ring
     assert e.value.code == -3
+
+
+def test_zero_row_marches_change_nothing():
+    """fdtd_march of 0 rows is a no-op at any point of the march (the row
+    counter stays, the result is bitwise that of the march without them)"""
+    inst = MARCH_CASES["gauss_D10_Nx2600"]
+    E = oracle.E_table(inst)
+    a = fdtd.Solver(inst).set_boundary(E)
+    a.march(inst.Nt)
+    b = fdtd.Solver(inst).set_boundary(E)
+    b.march(0)
+    assert b.row == 0
+    b.march(77)
+    b.march(0)
+    assert b.row == 77
+    b.march(inst.Nt - 77)
+    b.march(0)
+    assert b.row == inst.Nt
+    for rho in (inst.Nt - inst.D - 1, inst.Nt):
+        assert np.array_equal(a.row_values(rho), b.row_values(rho))
+    assert np.array_equal(a.pe(), b.pe())
+    a.close()
+    b.close()
+
